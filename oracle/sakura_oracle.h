@@ -1,0 +1,78 @@
+/*
+ * Sakura CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, fp64 reference of the Keplerian Hamiltonian splitting step
+ * (Goncalves Ferrari, Boekholt & Portegies Zwart 2014, Sec. 2).  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load this
+ * library.  It shares no source with the HIP library under
+ * paper_1402_3325_amd/csrc and must never be used as a compute fallback.
+ *
+ * All arrays are host memory.  Positions and velocities are [n][3] row-major
+ * doubles, masses [n] doubles.  Return codes: 0 ok, <0 error (values below).
+ */
+#ifndef SAKURA_ORACLE_H
+#define SAKURA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SREF_OK          0
+#define SREF_EINVAL     -1
+#define SREF_ENONFINITE -2
+#define SREF_ECOLLIDE   -3
+#define SREF_ENOCONV    -4
+
+/* Pair solvers usable inside the eq. (26) map. */
+#define SREF_SOLVER_KEPLER        0 /* universal-variable Kepler flow, increments in difference form */
+#define SREF_SOLVER_KEPLER_LITERAL 1 /* same flow, increments by the literal subtraction of Listing 1 */
+#define SREF_SOLVER_DKD           2 /* drift-kick-drift two-body map of eq. (28) */
+
+/* Stumpff functions c2(z), c3(z) of the universal-variable formulation. */
+double sref_stumpff_c2(double z);
+double sref_stumpff_c3(double z);
+
+/* Kepler flow of eq. (18): propagate the relative state (x0, w0) of a two-body
+ * problem with gravitational parameter mu over time tau.
+ * Outputs x1, w1 and coef = {f-1, g-tau, fdot, gdot-1} (Lagrange coefficients
+ * written as differences from the free-drift values).  iters may be NULL. */
+int sref_kepler(double tau, double mu, const double x0[3], const double w0[3],
+                double x1[3], double w1[3], double coef[4], int *iters);
+
+/* Relative increments (dr_ij, dv_ij) of one pair from the second-order pair map
+ * of eq. (26): back-drift by tau/2, pair flow over tau, back-drift by tau/2,
+ * minus the starting relative state.  ri, vi, rj, vj are the absolute
+ * (half-drifted) states. */
+int sref_pair_increment(double tau, double G, double mi, double mj,
+                        const double ri[3], const double vi[3],
+                        const double rj[3], const double vj[3], int solver,
+                        double dr[3], double dv[3]);
+
+/* One step Psi(tau) = T(tau/2) W(tau) T(tau/2), eqs. (27a-d), over ordered
+ * pairs as in Listing 1.  r and v are updated in place (left unchanged on
+ * error). */
+int sref_step(int64_t n, const double *m, double *r, double *v, double tau,
+              double G, int solver);
+
+/* The state after one step for the listed particles only (r, v unchanged). */
+int sref_step_rows(int64_t n, const double *m, const double *r, const double *v,
+                   double tau, double G, int64_t nrows, const int64_t *rows,
+                   double *r_out, double *v_out);
+
+/* nsteps calls of sref_step. */
+int sref_evolve(int64_t n, const double *m, double *r, double *v, double tau,
+                int64_t nsteps, double G, int solver);
+
+/* out[12] = {E, K, U, P[3], L[3], Rcm[3]} with long-double accumulation. */
+int sref_energy(int64_t n, const double *m, const double *r, const double *v,
+                double G, double out[12]);
+
+/* Number of OpenMP threads the row loops use. */
+int sref_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

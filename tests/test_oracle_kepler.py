@@ -1,0 +1,197 @@
+"""Pins of the oracle's Stumpff functions, Kepler flow (eq. 18) and pair map
+(eq. 26) against closed forms, identities and invariants."""
+import numpy as np
+import pytest
+
+from paper_1402_3325_amd import workloads
+from tests import pins
+
+LD = np.longdouble
+
+
+# ---------------------------------------------------------------- Stumpff
+def test_stumpff_special_values(oracle):
+    assert oracle.stumpff_c2(0.0) == 0.5
+    assert oracle.stumpff_c3(0.0) == 1.0 / 6.0
+    # c2(4 pi^2) = (1 - cos 2pi) / 4pi^2 = 0 ; c3(pi^2) = (pi - sin pi)/pi^3 = 1/pi^2
+    assert abs(oracle.stumpff_c2(4 * np.pi ** 2)) < 1e-17
+    assert abs(oracle.stumpff_c3(np.pi ** 2) * np.pi ** 2 - 1.0) < 4e-16
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_stumpff_closed_form(oracle, sign):
+    """Series and closed forms against long-double trigonometry."""
+    for z in sign * np.logspace(-10, 3.5, 400):
+        zl = LD(z)
+        if z > 0:
+            s = np.sqrt(zl)
+            c2 = (1 - np.cos(s)) / zl
+            c3 = (s - np.sin(s)) / (zl * s)
+        else:
+            s = np.sqrt(-zl)
+            c2 = (np.cosh(s) - 1) / (-zl)
+            c3 = (np.sinh(s) - s) / (-zl * s)
+        # near z = 0 the long-double closed form itself cancels: use its series
+        if abs(z) < 1e-3:
+            c2 = sum((-zl) ** k / np.prod(np.arange(1, 2 * k + 3, dtype=LD)) for k in range(8))
+            c3 = sum((-zl) ** k / np.prod(np.arange(1, 2 * k + 4, dtype=LD)) for k in range(8))
+        tol = 2e-15 if abs(z) < 30 else 1e-13
+        assert abs(oracle.stumpff_c2(z) - c2) <= tol * max(abs(c2), 1 / max(abs(z), 1)), z
+        assert abs(oracle.stumpff_c3(z) - c3) <= tol * max(abs(c3), 1 / max(abs(z), 1) ** 1.5), z
+
+
+def test_stumpff_doubling_identities(oracle):
+    """c2(4z) = c1(z)^2/2 and c3(4z) = (c2(z) + c0(z) c3(z))/4, with
+    c0 = 1 - z c2 and c1 = 1 - z c3 (the Stumpff recurrence)."""
+    for z in np.concatenate([np.linspace(-30, 9, 157), [-1e-6, 1e-6, 0.99, 1.01]]):
+        c2, c3 = oracle.stumpff_c2(z), oracle.stumpff_c3(z)
+        c0, c1 = 1 - z * c2, 1 - z * c3
+        assert abs(oracle.stumpff_c2(4 * z) - c1 * c1 / 2) <= 1e-14 * max(1.0, c1 * c1)
+        assert abs(oracle.stumpff_c3(4 * z) - (c2 + c0 * c3) / 4) <= 1e-14 * max(1.0, abs(c0 * c3))
+
+
+# ---------------------------------------------------------------- Kepler flow
+def test_kepler_circular_rotation(oracle):
+    """A circular orbit turns by n tau; the error may grow with the angle swept
+    (rounding of the period removed for multi-revolution flights)."""
+    for mu, a, tau in [(1.0, 1.0, 0.1), (3.0, 0.2, 1.7), (1e-4, 1e-4, 2.3e-3), (2.0, 5.0, -4.0)]:
+        n = np.sqrt(mu / a ** 3)
+        x0 = np.array([a, 0.0, 0.0])
+        w0 = np.array([0.0, a * n, 0.0])
+        x1, w1, _, _ = oracle.kepler(tau, mu, x0, w0)
+        th = np.sqrt(LD(mu) / LD(a) ** 3) * LD(tau)
+        tol = 4e-15 * (1.0 + abs(float(th)))
+        xr = np.array([a * np.cos(th), a * np.sin(th), 0.0], dtype=LD)
+        wr = np.array([-a * n * np.sin(th), a * n * np.cos(th), 0.0], dtype=LD)
+        assert float(np.max(np.abs(x1 - xr))) <= tol * a
+        assert float(np.max(np.abs(w1 - wr))) <= tol * a * n
+
+
+def _err(a, b, scale):
+    return float(np.max(np.abs(np.asarray(a, dtype=LD) - np.asarray(b, dtype=LD))) / scale)
+
+
+def test_kepler_vs_closed_form_elements(oracle):
+    """Universal variables vs Kepler's equation in eccentric/hyperbolic anomaly."""
+    mu, X, W, T, kind = workloads.kepler_cases(600)
+    worst = {}
+    for i in range(len(mu)):
+        if kind[i] == "parabolic":
+            continue  # the elements form is singular at zero energy
+        x1, w1, _, _ = oracle.kepler(T[i], mu[i], X[i], W[i])
+        xr, wr = pins.kepler_elements(T[i], mu[i], X[i], W[i])
+        ex = _err(x1, xr, max(np.linalg.norm(X[i]), float(np.sqrt(np.dot(xr, xr)))))
+        ew = _err(w1, wr, max(np.linalg.norm(W[i]), float(np.sqrt(np.dot(wr, wr)))))
+        worst[kind[i]] = max(worst.get(kind[i], 0.0), ex, ew)
+    # conditioning: eccentric orbits near pericentre and multi-period flights
+    # amplify rounding of the inputs; everything else is at a few ulps.
+    limits = {"elliptic": 1e-13, "hyperbolic": 1e-13, "distant": 1e-14,
+              "eccentric": 1e-10, "long": 1e-11}
+    for k, e in worst.items():
+        assert e < limits[k], (k, e, worst)
+
+
+def test_kepler_wronskian_and_invariants(oracle):
+    mu, X, W, T, kind = workloads.kepler_cases(600)
+    for i in range(len(mu)):
+        x1, w1, c, _ = oracle.kepler(T[i], mu[i], X[i], W[i])
+        f, g, fd, gd = 1 + c[0], T[i] + c[1], c[2], 1 + c[3]
+        # f gdot - fdot g = 1 (area preservation of the two-body flow)
+        scale = max(1.0, abs(f * gd), abs(fd * g))
+        assert abs(f * gd - fd * g - 1.0) <= 2e-13 * scale, (kind[i], f * gd - fd * g - 1)
+        e0 = 0.5 * W[i] @ W[i] - mu[i] / np.linalg.norm(X[i])
+        e1 = 0.5 * w1 @ w1 - mu[i] / np.linalg.norm(x1)
+        escale = max(0.5 * W[i] @ W[i], mu[i] / np.linalg.norm(X[i]))
+        tol = 1e-10 if kind[i] in ("eccentric", "long") else 1e-13
+        assert abs(e1 - e0) <= tol * escale, (kind[i], (e1 - e0) / escale)
+        h0 = np.cross(X[i], W[i])
+        h1 = np.cross(x1, w1)
+        hscale = np.linalg.norm(X[i]) * np.linalg.norm(W[i])
+        assert np.max(np.abs(h1 - h0)) <= tol * hscale, (kind[i],)
+
+
+def test_kepler_group_property(oracle):
+    """K(t1) K(t2) = K(t1 + t2) and K(-t) K(t) = identity."""
+    mu, X, W, T, kind = workloads.kepler_cases(300, kinds=("elliptic", "hyperbolic", "distant"))
+    for i in range(len(mu)):
+        xa, wa, _, _ = oracle.kepler(0.37 * T[i], mu[i], X[i], W[i])
+        xb, wb, _, _ = oracle.kepler(0.63 * T[i], mu[i], xa, wa)
+        xc, wc, _, _ = oracle.kepler(T[i], mu[i], X[i], W[i])
+        sx = max(np.linalg.norm(X[i]), np.linalg.norm(xc))
+        sw = max(np.linalg.norm(W[i]), np.linalg.norm(wc))
+        assert np.max(np.abs(xb - xc)) <= 1e-12 * sx
+        assert np.max(np.abs(wb - wc)) <= 1e-12 * sw
+        xr, wr, _, _ = oracle.kepler(-T[i], mu[i], xc, wc)
+        assert np.max(np.abs(xr - X[i])) <= 1e-12 * sx
+        assert np.max(np.abs(wr - W[i])) <= 1e-12 * sw
+
+
+def test_kepler_massless_is_free_drift(oracle):
+    x1, w1, c, _ = oracle.kepler(0.7, 0.0, [1.0, 2.0, 3.0], [0.1, -0.2, 0.3])
+    assert np.all(c == 0.0)
+    assert np.array_equal(w1, [0.1, -0.2, 0.3])
+    dr, dv = oracle.pair_increment(0.7, 1.0, 0.0, 0.0, [1, 2, 3], [0.1, -0.2, 0.3],
+                                   [0, 0, 0], [0, 0, 0])
+    assert np.all(dr == 0.0) and np.all(dv == 0.0)
+
+
+def test_kepler_collision_is_reported(oracle):
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.kepler(0.1, 1.0, [0.0, 0.0, 0.0], [1.0, 0.0, 0.0])
+    assert e.value.code == -3
+
+
+# ---------------------------------------------------------------- pair map (eq. 26)
+def _jerk(mu, X, W):
+    r2 = X @ X
+    r = np.sqrt(r2)
+    return -mu * (W / r ** 3 - 3 * (X @ W) * X / r ** 5)
+
+
+def test_pair_map_small_tau_expansion(oracle):
+    """dv_ij = tau a_ij(X) + O(tau^3) (a midpoint kick) and
+    dr_ij = -tau^3/12 j_ij(X) + O(tau^4): the two half back-drifts remove the
+    free drift and the first-order displacement."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        X = rng.normal(size=3)
+        W = rng.normal(size=3) * 0.5
+        mi, mj = rng.uniform(0.2, 1.0, 2)
+        mu = mi + mj
+        a = -mu * X / np.linalg.norm(X) ** 3
+        j = _jerk(mu, X, W)
+        errs_v, errs_r = [], []
+        for tau in (4e-3, 2e-3):
+            dr, dv = oracle.pair_increment(tau, 1.0, mi, mj, X, W, np.zeros(3), np.zeros(3))
+            errs_v.append(np.linalg.norm(dv / tau - a) / np.linalg.norm(a))
+            errs_r.append(np.linalg.norm(dr * 12 / tau ** 3 + j) / np.linalg.norm(j))
+        assert errs_v[0] < 1e-4 and errs_r[0] < 5e-2
+        assert 3.9 < errs_v[0] / errs_v[1] < 4.1      # O(tau^2) relative
+        assert 1.95 < errs_r[0] / errs_r[1] < 2.05    # O(tau) relative
+
+
+def test_pair_increment_antisymmetric_bitwise(oracle):
+    """Swapping i and j negates every input of the pair solve exactly, so the
+    increments are exact negatives: each unordered pair need be solved once."""
+    m, r, v, tau = workloads.planetary(15)
+    m2, r2, v2, tau2 = workloads.plummer(64, rng=np.random.default_rng(3))
+    for (mm, rr, vv, tt) in ((m, r, v, tau), (m2, r2, v2, tau2)):
+        for i in range(6):
+            for j in range(i + 1, 9):
+                a = oracle.pair_increment(tt, 1.0, mm[i], mm[j], rr[i], vv[i], rr[j], vv[j])
+                b = oracle.pair_increment(tt, 1.0, mm[j], mm[i], rr[j], vv[j], rr[i], vv[i])
+                assert np.array_equal(a[0], -b[0]) and np.array_equal(a[1], -b[1])
+
+
+def test_literal_and_difference_forms_agree(oracle):
+    """Listing 1's subtraction and the Lagrange-coefficient form differ only by
+    the rounding of the free drift, i.e. a few ulps of |X| + tau |W|."""
+    m, r, v, _ = workloads.plummer(128, rng=np.random.default_rng(5))
+    tau = 1e-2
+    for i in range(10):
+        for j in range(10, 20):
+            a = oracle.pair_increment(tau, 1.0, m[i], m[j], r[i], v[i], r[j], v[j], 0)
+            b = oracle.pair_increment(tau, 1.0, m[i], m[j], r[i], v[i], r[j], v[j], 1)
+            X = np.linalg.norm(r[i] - r[j]) + tau * np.linalg.norm(v[i] - v[j])
+            assert np.max(np.abs(a[0] - b[0])) <= 8 * 2.2e-16 * X
+            assert np.max(np.abs(a[1] - b[1])) <= 8 * 2.2e-16 * np.linalg.norm(v[i] - v[j])
