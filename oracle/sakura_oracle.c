@@ -90,7 +90,7 @@ typedef struct {
 } kepeq_t;
 
 static void kepeq_eval(const kepeq_t *k, double chi, double *F, double *dF,
-                       double *d2F)
+                       double *d2F, double *Fnoise)
 {
     double z = k->alpha * chi * chi;
     double C = sref_stumpff_c2(z), S = sref_stumpff_c3(z);
@@ -99,11 +99,16 @@ static void kepeq_eval(const kepeq_t *k, double chi, double *F, double *dF,
     *F = k->sig0 * U2 + k->q * U3 + k->r0 * chi - k->T;
     *dF = k->sig0 * U1 + k->q * U2 + k->r0;
     *d2F = k->sig0 * U0 + k->q * U1;
+    /* size of the rounding error of F: eps times the sum of its terms */
+    *Fnoise = EPS * (fabs(k->sig0 * U2) + fabs(k->q * U3) + fabs(k->r0 * chi) + fabs(k->T));
 }
 
 /* Root of F by the Laguerre iteration (order 5, as Conway uses for Kepler's
  * equation) inside a bracket that bisection falls back to whenever a Laguerre
- * step would leave it.  Returns 0 on convergence. */
+ * step would leave it.  Converged when the step or the bracket is below
+ * 4 eps |chi|, or when F is zero to within the rounding of its own terms (for
+ * ill-conditioned orbits the iterates can otherwise bounce between points a
+ * few ulps apart).  Returns 0 on convergence. */
 static int kepeq_solve(const kepeq_t *k, double *chi_out, int *iters)
 {
     const double nL = 5.0;
@@ -117,16 +122,19 @@ static int kepeq_solve(const kepeq_t *k, double *chi_out, int *iters)
     double chi = u - k->sig0 * u * u / (2.0 * k->r0) +
                  (3.0 * k->sig0 * k->sig0 - k->q * k->r0) * u * u * u /
                      (6.0 * k->r0 * k->r0);
-    if (!isfinite(chi) || (chi > 0.0) != (k->T > 0.0)) chi = u;
+    /* Beyond the reach of the series (its corrections dominate) start from the
+     * free-drift value u; the bracket search below doubles from there. */
+    if (!isfinite(chi) || (chi > 0.0) != (k->T > 0.0) || fabs(chi - u) > 0.5 * fabs(u))
+        chi = u;
 
     /* Bracket.  F(0) = -T, so the root has the sign of T. */
-    double lo, hi, F, dF, d2F;
+    double lo, hi, F, dF, d2F, Fn;
     int grow = 0;
     if (k->T > 0.0) {
         lo = 0.0;
         hi = chi;
         for (;;) {
-            kepeq_eval(k, hi, &F, &dF, &d2F);
+            kepeq_eval(k, hi, &F, &dF, &d2F, &Fn);
             if (!(F < 0.0)) break; /* F >= 0, or overflow far beyond the root */
             lo = hi;
             hi *= 2.0;
@@ -136,7 +144,7 @@ static int kepeq_solve(const kepeq_t *k, double *chi_out, int *iters)
         hi = 0.0;
         lo = chi;
         for (;;) {
-            kepeq_eval(k, lo, &F, &dF, &d2F);
+            kepeq_eval(k, lo, &F, &dF, &d2F, &Fn);
             if (!(F > 0.0)) break;
             hi = lo;
             lo *= 2.0;
@@ -146,8 +154,16 @@ static int kepeq_solve(const kepeq_t *k, double *chi_out, int *iters)
     if (!(chi >= lo && chi <= hi)) chi = 0.5 * (lo + hi);
 
     for (int it = 1; it <= 400; ++it) {
-        kepeq_eval(k, chi, &F, &dF, &d2F);
-        if (F == 0.0) {
+        kepeq_eval(k, chi, &F, &dF, &d2F, &Fn);
+        if (!isfinite(F) || !isfinite(dF)) {
+            /* The Stumpff functions overflow only far beyond the root: shrink
+             * the bracket from that side and bisect. */
+            if (k->T > 0.0) hi = chi;
+            else lo = chi;
+            chi = 0.5 * (lo + hi);
+            continue;
+        }
+        if (fabs(F) <= 2.0 * Fn) {
             *chi_out = chi;
             if (iters) *iters = it;
             return 0;

@@ -195,3 +195,23 @@ def test_literal_and_difference_forms_agree(oracle):
             X = np.linalg.norm(r[i] - r[j]) + tau * np.linalg.norm(v[i] - v[j])
             assert np.max(np.abs(a[0] - b[0])) <= 8 * 2.2e-16 * X
             assert np.max(np.abs(a[1] - b[1])) <= 8 * 2.2e-16 * np.linalg.norm(v[i] - v[j])
+
+
+def test_kepler_strongly_hyperbolic_flights(oracle):
+    """Flights with sqrt(-beta) |tau| / r0 up to ~40, where the Stumpff
+    functions grow like exp(40) and overflow anywhere near a poor iterate:
+    the result must stay finite and match Kepler's hyperbolic equation."""
+    rng = np.random.default_rng(21)
+    for _ in range(120):
+        mu = 10.0 ** rng.uniform(-4, 0)
+        r0 = 10.0 ** rng.uniform(-3, 0)
+        x = r0 * workloads._isotropic(rng, 1)[0]
+        speed = np.sqrt(mu / r0) * 10.0 ** rng.uniform(0.3, 2.0)
+        w = speed * workloads._isotropic(rng, 1)[0]
+        k = np.sqrt(speed ** 2 - 2 * mu / r0)
+        tau = rng.choice([-1.0, 1.0]) * r0 / k * 10.0 ** rng.uniform(0.7, 1.6)
+        x1, w1, c, _ = oracle.kepler(tau, mu, x, w)
+        assert np.all(np.isfinite(c)) and np.all(np.isfinite(x1))
+        xr, wr = pins.kepler_elements(tau, mu, x, w)
+        sx = max(r0, float(np.sqrt(xr @ xr)))
+        assert _err(x1, xr, sx) < 1e-13 and _err(w1, wr, float(np.sqrt(wr @ wr))) < 1e-13
