@@ -1,0 +1,155 @@
+"""Benchmark: Kepler pair-solves/s of the Sakura step at N = 16384 (FP64).
+
+Workload: a star cluster of 16383 Plummer stars (total mass 1, 10 % in
+primordial binaries with a log-uniform in [1e-4, 1e-2] and thermal
+eccentricities) around a central point mass 0.01, tau = 1/2048.  One "step" is
+one full pass of eqs. (27a-d): the half drifts and all N(N-1)/2 pair solves
+with their weighted two-sided sums.  The timed region is one sakura_evolve call
+of K steps with the state already resident in HBM.
+
+Prints one JSON line (see the fields below).  --gpus N > 1 is refused: this
+build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Kepler pair-solves/s at N=16384 (FP64), learned-guess vs plain at 1e-12 error"
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+
+# Algorithmic FP64 operations per pair solve, counted in the kernel source
+# (add/sub/mul/div/sqrt = 1, fma = 2): pair setup and back-drift 19, Kepler
+# set-up and starter 38, one Laguerre iteration 63, Lagrange coefficients 12,
+# increments, weights and the two-sided sums 49.
+FLOPS_FIXED = 19 + 38 + 12 + 49
+FLOPS_PER_ITER = 63
+
+
+def flops_per_pair(mean_iters):
+    return FLOPS_FIXED + FLOPS_PER_ITER * mean_iters
+
+
+def parity_sample(lib, torch, m, r, v, tau, rows):
+    """One GPU step vs the oracle on sampled rows (per-step error metric)."""
+    import oracle
+    mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
+    lib.evolve(mt, rt, vt, tau, 1)
+    rg, vg = rt.cpu().numpy()[rows], vt.cpu().numpy()[rows]
+    ro, vo = oracle.step_rows(m, r, v, tau, rows)
+    r_rms = np.sqrt(np.mean(np.sum(r ** 2, 1)))
+    v_rms = np.sqrt(np.mean(np.sum(v ** 2, 1)))
+    er = np.max(np.linalg.norm(rg - ro, axis=1) / np.maximum(np.linalg.norm(ro, axis=1), r_rms))
+    ev = np.max(np.linalg.norm(vg - vo, axis=1) / np.maximum(np.linalg.norm(vo, axis=1), v_rms))
+    return float(er), float(ev)
+
+
+def cpu_baseline(m, r, v, tau, budget_s=15.0):
+    """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
+    a bounded sample: rows of one step of the same workload."""
+    import oracle
+    n = len(m)
+    probe = np.arange(0, n, max(1, n // 128))
+    t0 = time.perf_counter()
+    oracle.step_rows(m, r, v, tau, probe)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    nrows = int(min(n, max(len(probe), budget_s / max(per_row, 1e-9))))
+    rows = np.linspace(0, n - 1, nrows).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.step_rows(m, r, v, tau, rows)
+    el = time.perf_counter() - t0
+    solves = nrows * (n - 1)
+    return {"value": solves / el, "unit": "pair-solves/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{nrows} of {n} rows of one step of the same workload "
+                      f"({solves} ordered pair solves, each pair solved from both "
+                      f"ends as in Listing 1), {el:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with HBM bytes per pair launch from rocprofv3 counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; --gpus N > 1 is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1402_3325_amd import workloads
+    from paper_1402_3325_amd.sakura import Sakura
+
+    m, r, v, tau, _ = workloads.config(2)
+    n = len(m)
+    pairs = n * (n - 1) // 2
+    lib = Sakura(0)
+
+    parity = None
+    if not args.no_parity:
+        rows = np.unique(np.concatenate([[0], np.random.default_rng(11).choice(n, 63, replace=False)]))
+        er, ev = parity_sample(lib, torch, m, r, v, tau, rows)
+        parity = {"err_r": er, "err_v": ev, "rows": int(len(rows)), "tol": 1e-12}
+
+    mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
+    if args.warmup:
+        lib.evolve(mt, rt, vt, tau, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = lib.evolve(mt, rt, vt, tau, args.steps, stats=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    k_mean = st["iters_total"] / max(st["pair_solves"], 1)
+    pair_ms = st["pair_kernel_ms"] / max(st["pair_launches"], 1)
+    fl = flops_per_pair(k_mean) * pairs
+    achieved = fl / (pair_ms * 1e-3) / 1e12
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": pairs * args.steps / wall,
+        "unit": "pair-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cluster: 16383 Plummer stars (10% in binaries) + central "
+                               "mass 0.01, N=16384, tau=1/2048",
+                   "n": n, "pairs_per_step": pairs, "guess": "analytic"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic},
+        "pair_kernel_ms": pair_ms,
+        "call_ms_events": st["call_ms"],
+        "mean_kepler_iters": k_mean,
+        "max_kepler_iters": st["iters_max"],
+        "fallbacks": st["fallbacks"],
+        "flops_per_pair": flops_per_pair(k_mean),
+        "err_vs_oracle": parity,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, r, v, tau)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

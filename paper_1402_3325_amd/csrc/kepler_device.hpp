@@ -1,0 +1,181 @@
+// Two-body (Kepler) flow of one pair for the Sakura pair map, in FP64.
+//
+// The paper evolves every pair with a universal-variable Kepler solver
+// (Sec. 2.3, eq. 18) and then removes the free drift of the two half
+// back-drifts of eq. (26).  This device routine writes the same flow through
+// Stumpff's G-functions of the regularised time s (dt/ds = r):
+//
+//   G_k(s) = s^k c_k(beta s^2),  beta = 2 mu / r0 - |w0|^2,  eta = x0 . w0,
+//   t(s)   = r0 G1 + eta G2 + mu G3 = r0 s + eta G2 + zeta G3,
+//   r(s)   = dt/ds = r0 + eta G1 + zeta G2 > 0,   zeta = mu - beta r0,
+//
+// (the second forms use G1 = s - beta G3 and G0 = 1 - beta G2),
+//
+// and solves t(s) = tau with a Laguerre iteration (order 5, as Conway 1986
+// does for Kepler's equation), safeguarded by a bracket on the monotone t(s).
+// From the root it forms the Lagrange coefficients as differences from the
+// free drift (f-1, g-tau, fdot, gdot-1), so that the pair increments
+//
+//   dr = (f-1 - fdot tau/2) x0 + (g-tau - (gdot-1) tau/2) w0
+//   dv = fdot x0 + (gdot-1) w0
+//
+// carry no cancellation of the drift.  There is one code path for elliptic,
+// parabolic and hyperbolic motion: the Stumpff functions come from a fixed
+// seven-term series after quartering the argument, rebuilt with the doubling
+// identities, so typical pairs (|beta s^2| << 1) take no data-dependent branch.
+#pragma once
+
+#ifndef SAKURA_HD
+#define SAKURA_HD __device__
+#endif
+
+namespace kep {
+
+struct KeplerParams {
+    double tol;   // relative convergence tolerance on s
+    int max_iter; // Laguerre iterations before the pair is declared unconverged
+};
+
+// c2(z), c3(z) from sum_m (-z)^m / (2m+k)! for |z| <= 1/4 (seven terms leave a
+// truncation below 0.05 ulp), extended to any z by c2(4z) = c1(z)^2 / 2 and
+// c3(4z) = (c2(z) + c0(z) c3(z)) / 4 with c0 = 1 - z c2, c1 = 1 - z c3.
+SAKURA_HD inline void stumpff23(double z, double &c2, double &c3)
+{
+    int k = 0;
+    double zr = z;
+    // exact scaling by powers of two; the bound keeps z = +-inf from looping
+    // (1100 quarterings span the whole double range)
+    while (fabs(zr) > 0.25 && k < 1100) {
+        zr *= 0.25;
+        ++k;
+    }
+    c2 = 1.0 / 87178291200.0;            // 1/14!
+    c2 = fma(c2, -zr, 1.0 / 479001600.0); // 1/12!
+    c2 = fma(c2, -zr, 1.0 / 3628800.0);   // 1/10!
+    c2 = fma(c2, -zr, 1.0 / 40320.0);     // 1/8!
+    c2 = fma(c2, -zr, 1.0 / 720.0);       // 1/6!
+    c2 = fma(c2, -zr, 1.0 / 24.0);        // 1/4!
+    c2 = fma(c2, -zr, 0.5);               // 1/2!
+    c3 = 1.0 / 1307674368000.0;           // 1/15!
+    c3 = fma(c3, -zr, 1.0 / 6227020800.0); // 1/13!
+    c3 = fma(c3, -zr, 1.0 / 39916800.0);   // 1/11!
+    c3 = fma(c3, -zr, 1.0 / 362880.0);     // 1/9!
+    c3 = fma(c3, -zr, 1.0 / 5040.0);       // 1/7!
+    c3 = fma(c3, -zr, 1.0 / 120.0);        // 1/5!
+    c3 = fma(c3, -zr, 1.0 / 6.0);          // 1/3!
+    for (; k > 0; --k) {
+        double c0 = fma(-zr, c2, 1.0);
+        double c1 = fma(-zr, c3, 1.0);
+        c3 = 0.25 * fma(c0, c3, c2);
+        c2 = 0.5 * c1 * c1;
+        zr *= 4.0;
+    }
+}
+
+struct PairFlow {
+    double fm1, gmt, fdot, gdm1; // f-1, g-tau, fdot, gdot-1
+    int iters;
+    bool converged;
+    bool safeguarded; // a bisection or bracket-expansion step was needed
+};
+
+// Kepler flow over tau of the relative state (x0, w0) with parameter mu > 0 and
+// r0 = |x0| > 0 (callers substitute a trivial problem otherwise).
+SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1,
+                                      double x2, double w0, double w1, double w2,
+                                      const KeplerParams &kp)
+{
+    const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+    const double r0 = sqrt(r0sq);
+    const double eta = fma(x0, w0, fma(x1, w1, x2 * w2));
+    const double vsq = fma(w0, w0, fma(w1, w1, w2 * w2));
+    const double beta = 2.0 * mu / r0 - vsq;
+    const double zeta = fma(-beta, r0, mu); // mu - beta r0 = d^2 r / ds^2 at s = 0
+
+    // Bound motion repeats after P = 2 pi mu / beta^{3/2}: a flight longer than
+    // half a period is replaced by its remainder.
+    // sqrt(beta) s is the change of eccentric anomaly, so one period spans
+    // s = 2 pi / sqrt(beta); with |t| <= P/2 the root lies inside that span.
+    double t = tau;
+    double s_half = 1e300; // bound on |s| (bound orbits only)
+    if (beta > 0.0) {
+        const double sb = sqrt(beta);
+        s_half = 6.3 / sb; // just above 2 pi / sqrt(beta)
+        const double P = 6.283185307179586 * mu / (beta * sb);
+        if (fabs(t) > 0.5 * P) t -= P * rint(t / P);
+    }
+
+    // Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  Deep
+    // in the hyperbolic regime (-beta u^2 > 1) the series overshoots; there
+    // t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3) with k = sqrt(-beta)
+    // is inverted instead.
+    const double u = t / r0;
+    const double c3s = (3.0 * eta * eta - zeta * r0) / (6.0 * r0sq);
+    double s = u * fma(u * u, c3s, fma(-0.5 * eta / r0, u, 1.0));
+    if (beta < 0.0 && -beta * u * u > 1.0) {
+        const double k = sqrt(-beta);
+        const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
+        s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
+    }
+    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = u;
+    s = fmin(fmax(s, -s_half), s_half);
+
+    // The root has the sign of t since t(0) = 0 and t(s) increases.  For
+    // unbound motion the far end of the bracket stays open (+-1e300).
+    double lo = (t > 0.0) ? 0.0 : -s_half;
+    double hi = (t > 0.0) ? s_half : 0.0;
+
+    double G1 = 0.0, G2 = 0.0, G3 = 0.0, r = r0;
+    PairFlow out;
+    out.converged = false;
+    out.safeguarded = false;
+    double ds_prev = 1e300, F_prev = 1e300;
+    int it = 0;
+    while (it < kp.max_iter) {
+        ++it;
+        const double z = beta * s * s;
+        double c2, c3;
+        stumpff23(z, c2, c3);
+        const double s2 = s * s;
+        G1 = s * fma(-z, c3, 1.0);
+        G2 = s2 * c2;
+        G3 = s2 * s * c3;
+        const double G0 = fma(-z, c2, 1.0);
+        const double F = fma(r0, s, fma(eta, G2, fma(zeta, G3, -t)));
+        r = fma(eta, G1, fma(zeta, G2, r0));
+        const double Fpp = fma(eta, G0, zeta * G1);
+        if (F < 0.0) lo = s;
+        else hi = s;
+        const double disc = fma(16.0 * r, r, -20.0 * F * Fpp);
+        const double ds = 5.0 * F / (r + sqrt(fabs(disc)));
+        // Converged when the correction is below tol |s|, or when it sits at
+        // the rounding floor of F (tiny and no longer shrinking).
+        const double ads = fabs(ds), as = fabs(s);
+        if (ads <= kp.tol * as || F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * ds_prev)) {
+            out.converged = true;
+            break;
+        }
+        ds_prev = ads;
+        double sn = s - ds;
+        // Bisect when the step leaves the bracket or the residual fails to halve
+        // (a slow crawl down an exponential); an open bracket is expanded.
+        const bool stall = fabs(F) > 0.5 * F_prev && ads > 1e-6 * as;
+        if (!(sn >= lo && sn <= hi) || stall) {
+            sn = (hi - lo < 1e299) ? 0.5 * (lo + hi) : 2.0 * s;
+            out.safeguarded = true;
+        }
+        F_prev = fabs(F);
+        s = sn;
+    }
+    out.iters = it;
+    // Coefficients at the converged s (the last correction was below tol |s|).
+    const double rinv = 1.0 / r;
+    const double r0inv = 1.0 / r0;
+    out.fm1 = -mu * G2 * r0inv;
+    out.gmt = (t - tau) - mu * G3;
+    out.fdot = -mu * G1 * rinv * r0inv;
+    out.gdm1 = -mu * G2 * rinv;
+    return out;
+}
+
+} // namespace kep

@@ -1,0 +1,648 @@
+// Sakura step on MI355X (gfx950): kernels and the C ABI of include/sakura.h.
+//
+// Data layout in HBM (library-owned, per handle):
+//   state[10][np] float64 structure-of-arrays, np = 64 * ceil(n / 64):
+//     row 0 m, rows 1-3 r (after the step), rows 4-6 v, rows 7-9 r half-drifted
+//   part[nb][nb][6][64] float64: part[K][L][c][l] = sum over the 64 particles of
+//     block L of the weighted increment component c (dr xyz, dv xyz) received by
+//     particle 64 K + l from pairs with block L (the diagonal block for L = K).
+// Per step: k_pairs (eqs. 26, 23 over all unordered pairs) then k_apply
+// (eqs. 27b-d and the next step's 27a); k_import / k_export convert between the
+// caller's [n][3] arrays and the internal layout once per call.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sakura.h"
+#include "kepler_device.hpp"
+
+namespace {
+
+constexpr int TILE = 64; // particles per block = lanes per wavefront
+
+enum : unsigned { ST_NONFINITE = 1u, ST_COLLIDE = 2u, ST_NOCONV = 4u, ST_INVAL = 8u };
+
+struct DevCounters {
+    unsigned status; // ST_* bits
+    unsigned iters_max;
+    unsigned long long pair_solves;
+    unsigned long long iters_total;
+    unsigned long long fallbacks;
+    long long failed_step;
+    unsigned hist[32];
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ inline unsigned wave_sum(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline unsigned wave_max(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = max(x, (unsigned)__shfl_xor(x, o, 64));
+    return x;
+}
+__device__ inline unsigned wave_or(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x |= (unsigned)__shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline double wave_sum_d(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ inline void record_error(DevCounters *c, unsigned bits, long long step)
+{
+    atomicOr(&c->status, bits);
+    atomicMin(&c->failed_step, step);
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_clear(DevCounters *c)
+{
+    const int t = threadIdx.x;
+    if (t == 0) {
+        c->status = 0;
+        c->iters_max = 0;
+        c->pair_solves = 0;
+        c->iters_total = 0;
+        c->fallbacks = 0;
+        c->failed_step = LLONG_MAX;
+    }
+    if (t < 32) c->hist[t] = 0;
+}
+
+// Caller layout -> SoA, with the half drift of eq. (27a) into the row r_half.
+__global__ void k_import(int n, int np, const double *__restrict__ m,
+                         const double *__restrict__ r, const double *__restrict__ v,
+                         double h, double *__restrict__ S, DevCounters *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    double mi = 0.0, p[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+        mi = m[i];
+        for (int c = 0; c < 3; ++c) {
+            p[c] = r[3 * i + c];
+            q[c] = v[3 * i + c];
+        }
+        bool fin = isfinite(mi);
+        for (int c = 0; c < 3; ++c) fin = fin && isfinite(p[c]) && isfinite(q[c]);
+        if (!fin) record_error(cnt, ST_NONFINITE, 0);
+        else if (!(mi >= 0.0)) record_error(cnt, ST_INVAL, 0);
+    }
+    S[i] = mi;
+    for (int c = 0; c < 3; ++c) {
+        S[(1 + c) * (size_t)np + i] = p[c];
+        S[(4 + c) * (size_t)np + i] = q[c];
+        S[(7 + c) * (size_t)np + i] = p[c] + h * q[c];
+    }
+}
+
+// All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
+//
+// Lane l holds particle i = 64 I + l; block J sits in LDS.  In sub-step s lane
+// l takes the pair (i, 64 J + ((l + s) mod 64)), so within a sub-step every
+// lane touches a different j and the j-side sums (Newton's third law) are
+// updated in LDS without conflicts or atomics.  The diagonal tile runs
+// s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
+// Partial sums go to part[I][J] (i side) and part[J][I] (j side).
+template <bool HIST>
+__global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double tau,
+                                                double G, const double *__restrict__ S,
+                                                double *__restrict__ part,
+                                                DevCounters *cnt, kep::KeplerParams kp,
+                                                long long step)
+{
+    if (cnt->status) return; // an earlier failure: the call will report it
+    const int t = blockIdx.x;
+    const int noff = nb * (nb - 1) / 2;
+    int I, J;
+    if (t < noff) { // off-diagonal tiles first (twice the work of a diagonal one)
+        int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+        while (j * (j - 1) / 2 > t) --j;
+        while ((j + 1) * j / 2 <= t) ++j;
+        J = j;
+        I = t - j * (j - 1) / 2;
+    } else {
+        I = J = t - noff;
+    }
+    const bool diag = (I == J);
+    const int lane = threadIdx.x;
+
+    const double *M = S;
+    const double *V = S + 4 * (size_t)np;
+    const double *XH = S + 7 * (size_t)np;
+
+    __shared__ double sj[7][TILE]; // x y z vx vy vz m of block J
+    __shared__ double sa[6][TILE]; // j-side sums
+    __shared__ unsigned shist[HIST ? 32 : 1];
+
+    const int jg = J * TILE + lane;
+    sj[0][lane] = XH[jg];
+    sj[1][lane] = XH[np + jg];
+    sj[2][lane] = XH[2 * (size_t)np + jg];
+    sj[3][lane] = V[jg];
+    sj[4][lane] = V[np + jg];
+    sj[5][lane] = V[2 * (size_t)np + jg];
+    sj[6][lane] = M[jg];
+    for (int c = 0; c < 6; ++c) sa[c][lane] = 0.0;
+    if (HIST && lane < 32) shist[lane] = 0;
+
+    const int ig = I * TILE + lane;
+    const double xi = XH[ig], yi = XH[np + ig], zi = XH[2 * (size_t)np + ig];
+    const double ui = V[ig], vi = V[np + ig], wi = V[2 * (size_t)np + ig];
+    const double mi = M[ig];
+    const bool valid_i = ig < n;
+    const double h = 0.5 * tau;
+
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned it_sum = 0, it_max = 0, n_solve = 0, n_fb = 0, flags = 0;
+    __syncthreads();
+
+    const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
+    for (int s = s0; s < s1; ++s) {
+        const int q = (lane + s) & (TILE - 1);
+        const double mj = sj[6][q];
+        const double msum = mi + mj;
+        const bool act = valid_i && (J * TILE + q < n) && (msum > 0.0) &&
+                         !(diag && s == TILE / 2 && lane >= TILE / 2);
+        // relative state and the pair back-drift of eq. (17) by tau/2
+        const double W0 = ui - sj[3][q], W1 = vi - sj[4][q], W2 = wi - sj[5][q];
+        double x0 = fma(-h, W0, xi - sj[0][q]);
+        double x1 = fma(-h, W1, yi - sj[1][q]);
+        double x2 = fma(-h, W2, zi - sj[2][q]);
+        const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+        const bool collide = act && !(r0sq > 0.0);
+        const bool live = act && !collide;
+        // lanes without a pair solve a trivial problem (tau = 0, mu = 0)
+        const double tt = live ? tau : 0.0;
+        const double mu = live ? G * msum : 0.0;
+        x0 = live ? x0 : 1.0;
+        x1 = live ? x1 : 0.0;
+        x2 = live ? x2 : 0.0;
+        const double w0 = live ? W0 : 0.0, w1 = live ? W1 : 0.0, w2 = live ? W2 : 0.0;
+
+        const kep::PairFlow f = kep::kepler_flow(tt, mu, x0, x1, x2, w0, w1, w2, kp);
+
+        // increments of eq. (26) minus the starting relative state
+        const double a = fma(-h, f.fdot, f.fm1);
+        const double b = fma(-h, f.gdm1, f.gmt);
+        const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
+                             fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
+                             fma(f.fdot, x2, f.gdm1 * w2)};
+        // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j)
+        const double inv = live ? 1.0 / msum : 0.0;
+        const double wgt_i = mj * inv, wgt_j = mi * inv;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            acc[c] = fma(wgt_i, d[c], acc[c]);
+            sa[c][q] = fma(-wgt_j, d[c], sa[c][q]);
+        }
+        if (live) {
+            ++n_solve;
+            it_sum += f.iters;
+            it_max = max(it_max, (unsigned)f.iters);
+            n_fb += f.safeguarded ? 1u : 0u;
+            if (!f.converged) flags |= ST_NOCONV;
+            if (HIST) atomicAdd(&shist[min(f.iters, 31)], 1u);
+        }
+        if (collide) flags |= ST_COLLIDE;
+        __syncthreads(); // j-side sums of this sub-step visible to the next
+    }
+
+    const size_t cs = TILE; // component stride inside a partial
+    double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
+    if (diag) {
+        for (int c = 0; c < 6; ++c) pij[c * cs] = acc[c] + sa[c][lane];
+    } else {
+        double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
+        for (int c = 0; c < 6; ++c) {
+            pij[c * cs] = acc[c];
+            pji[c * cs] = sa[c][lane];
+        }
+    }
+
+    n_solve = wave_sum(n_solve);
+    it_sum = wave_sum(it_sum);
+    n_fb = wave_sum(n_fb);
+    it_max = wave_max(it_max);
+    flags = wave_or(flags);
+    if (lane == 0) {
+        atomicAdd(&cnt->pair_solves, (unsigned long long)n_solve);
+        atomicAdd(&cnt->iters_total, (unsigned long long)it_sum);
+        atomicAdd(&cnt->fallbacks, (unsigned long long)n_fb);
+        atomicMax(&cnt->iters_max, it_max);
+        if (flags) record_error(cnt, flags, step);
+    }
+    if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
+}
+
+// Deterministic compensated reduction of the partial sums of one block K
+// (fixed order L = 0..nb-1, TwoSum), then eqs. (27b-d) and the half drift
+// (27a) of the next step.  Wave c of the workgroup reduces component c.
+__global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, double h,
+                                                    double *__restrict__ S,
+                                                    const double *__restrict__ part,
+                                                    DevCounters *cnt, long long step)
+{
+    const int K = blockIdx.x;
+    const int c = threadIdx.x / TILE, lane = threadIdx.x % TILE;
+    __shared__ double dsum[6][TILE];
+    const double *p = part + ((size_t)K * nb * 6 + c) * TILE + lane;
+    double s = 0.0, e = 0.0;
+    for (int L = 0; L < nb; ++L) {
+        const double x = p[(size_t)L * 6 * TILE];
+        const double t = s + x;
+        const double bp = t - s;
+        e += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+    dsum[c][lane] = s + e;
+    __syncthreads();
+    if (c != 0) return;
+    const int i = K * TILE + lane;
+    if (i >= n) return;
+    double *X = S + (size_t)np, *V = S + 4 * (size_t)np, *XH = S + 7 * (size_t)np;
+    bool fin = true;
+    for (int k = 0; k < 3; ++k) {
+        const size_t o = (size_t)k * np + i;
+        const double rt = XH[o] + dsum[k][lane];    // (27b)
+        const double v1 = V[o] + dsum[3 + k][lane]; // (27c)
+        const double x1 = rt + h * v1;              // (27d)
+        X[o] = x1;
+        V[o] = v1;
+        XH[o] = x1 + h * v1; // (27a) of the next step
+        fin = fin && isfinite(x1) && isfinite(v1);
+    }
+    if (!fin) record_error(cnt, ST_NONFINITE, step);
+}
+
+// SoA -> caller layout, only when every step succeeded.
+__global__ void k_export(int n, int np, const double *__restrict__ S, double *__restrict__ r,
+                         double *__restrict__ v, const DevCounters *cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || cnt->status) return;
+    for (int c = 0; c < 3; ++c) {
+        r[3 * i + c] = S[(1 + c) * (size_t)np + i];
+        v[3 * i + c] = S[(4 + c) * (size_t)np + i];
+    }
+}
+
+// --- energy diagnostics -----------------------------------------------------
+// U: the same triangle of tiles; each tile writes sum_{pairs} m_i m_j / r_ij.
+__global__ __launch_bounds__(TILE) void k_energy_pairs(int n, int nb, const double *__restrict__ m,
+                                                       const double *__restrict__ r,
+                                                       double *__restrict__ tile_u)
+{
+    const int t = blockIdx.x;
+    const int noff = nb * (nb - 1) / 2;
+    int I, J;
+    if (t < noff) {
+        int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+        while (j * (j - 1) / 2 > t) --j;
+        while ((j + 1) * j / 2 <= t) ++j;
+        J = j;
+        I = t - j * (j - 1) / 2;
+    } else {
+        I = J = t - noff;
+    }
+    const int lane = threadIdx.x;
+    __shared__ double sj[4][TILE];
+    const int jg = J * TILE + lane;
+    const bool vj = jg < n;
+    sj[0][lane] = vj ? r[3 * jg] : 0.0;
+    sj[1][lane] = vj ? r[3 * jg + 1] : 0.0;
+    sj[2][lane] = vj ? r[3 * jg + 2] : 0.0;
+    sj[3][lane] = vj ? m[jg] : 0.0;
+    const int ig = I * TILE + lane;
+    const bool vi = ig < n;
+    const double xi = vi ? r[3 * ig] : 0.0, yi = vi ? r[3 * ig + 1] : 0.0,
+                 zi = vi ? r[3 * ig + 2] : 0.0, mi = vi ? m[ig] : 0.0;
+    __syncthreads();
+    double u = 0.0;
+    for (int q = 0; q < TILE; ++q) {
+        const int j = J * TILE + q;
+        const bool act = vi && j < n && (I != J || q > lane);
+        const double dx = xi - sj[0][q], dy = yi - sj[1][q], dz = zi - sj[2][q];
+        const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double term = act ? sj[3][q] / sqrt(d2) : 0.0;
+        u += term;
+    }
+    u = wave_sum_d(mi * u);
+    if (lane == 0) tile_u[t] = u;
+}
+
+// Per-block sums of K, M, P, L, M r (11 values) for the one-body terms.
+__global__ __launch_bounds__(TILE) void k_energy_bodies(int n, const double *__restrict__ m,
+                                                        const double *__restrict__ r,
+                                                        const double *__restrict__ v,
+                                                        double *__restrict__ blk)
+{
+    const int i = blockIdx.x * TILE + threadIdx.x;
+    double q[11];
+    for (int k = 0; k < 11; ++k) q[k] = 0.0;
+    if (i < n) {
+        const double mi = m[i];
+        const double x = r[3 * i], y = r[3 * i + 1], z = r[3 * i + 2];
+        const double a = v[3 * i], b = v[3 * i + 1], c = v[3 * i + 2];
+        q[0] = 0.5 * mi * (a * a + b * b + c * c);
+        q[1] = mi;
+        q[2] = mi * a;
+        q[3] = mi * b;
+        q[4] = mi * c;
+        q[5] = mi * (y * c - z * b);
+        q[6] = mi * (z * a - x * c);
+        q[7] = mi * (x * b - y * a);
+        q[8] = mi * x;
+        q[9] = mi * y;
+        q[10] = mi * z;
+    }
+    for (int k = 0; k < 11; ++k) {
+        const double s = wave_sum_d(q[k]);
+        if (threadIdx.x == 0) blk[(size_t)blockIdx.x * 11 + k] = s;
+    }
+}
+
+// Compensated, fixed-order totals: out = {E, K, U, P[3], L[3], Rcm[3]}.
+__global__ void k_energy_final(int ntiles, int nblk, double G, const double *__restrict__ tile_u,
+                               const double *__restrict__ blk, double *__restrict__ out)
+{
+    const int k = threadIdx.x; // 0 -> U, 1..11 -> body sums, others idle
+    double s = 0.0, e = 0.0;
+    const int cnt = (k == 0) ? ntiles : (k < 12 ? nblk : 0);
+    for (int t = 0; t < cnt; ++t) {
+        const double x = (k == 0) ? tile_u[t] : blk[(size_t)t * 11 + (k - 1)];
+        const double y = s + x;
+        const double bp = y - s;
+        e += (s - (y - bp)) + (x - bp);
+        s = y;
+    }
+    __shared__ double tot[12];
+    if (k < 12) tot[k] = s + e;
+    __syncthreads();
+    if (k == 0) {
+        const double U = -G * tot[0], K = tot[1], M = tot[2];
+        out[0] = K + U;
+        out[1] = K;
+        out[2] = U;
+        for (int c = 0; c < 3; ++c) {
+            out[3 + c] = tot[3 + c];
+            out[6 + c] = tot[6 + c];
+            out[9 + c] = M > 0.0 ? tot[9 + c] / M : 0.0;
+        }
+    }
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct sakura {
+    int device = 0;
+    sakura_opts opts{};
+    std::string err;
+    double *state = nullptr; // [10][np]
+    int64_t cap_np = 0;
+    double *part = nullptr; // [nb][nb][6][64]
+    int64_t cap_part = 0;
+    double *scratch_e = nullptr; // energy partials
+    int64_t cap_e = 0;
+    DevCounters *cnt = nullptr;
+    DevCounters *host_cnt = nullptr; // pinned
+    double *host_out = nullptr;      // pinned, 12 doubles
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+int fail(sakura_t *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define SAKURA_HIP(h, call)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((h), SAKURA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int grow(sakura_t *h, double **buf, int64_t *cap, int64_t need)
+{
+    if (*cap >= need) return SAKURA_OK;
+    if (*buf) {
+        SAKURA_HIP(h, hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    if (hipMalloc((void **)buf, (size_t)need * sizeof(double)) != hipSuccess) {
+        *buf = nullptr;
+        return fail(h, SAKURA_ENOMEM, "device allocation of " +
+                                          std::to_string((size_t)need * sizeof(double)) +
+                                          " bytes failed");
+    }
+    *cap = need;
+    return SAKURA_OK;
+}
+
+int need_events(sakura_t *h, size_t count)
+{
+    while (h->events.size() < count) {
+        hipEvent_t e;
+        SAKURA_HIP(h, hipEventCreate(&e));
+        h->events.push_back(e);
+    }
+    return SAKURA_OK;
+}
+
+int status_code(unsigned st)
+{
+    if (st & ST_INVAL) return SAKURA_EINVAL;
+    if (st & ST_NONFINITE) return SAKURA_ENONFINITE;
+    if (st & ST_COLLIDE) return SAKURA_ECOLLIDE;
+    if (st & ST_NOCONV) return SAKURA_ENOCONV;
+    return SAKURA_OK;
+}
+
+const char *status_text(int code)
+{
+    switch (code) {
+    case SAKURA_EINVAL: return "negative mass";
+    case SAKURA_ENONFINITE: return "non-finite position, velocity or mass";
+    case SAKURA_ECOLLIDE: return "two particles at zero separation (no softening)";
+    case SAKURA_ENOCONV: return "a Kepler solve did not converge";
+    default: return "";
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
+{
+    if (!out) return SAKURA_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return SAKURA_EINVAL;
+    sakura_t *h = new sakura();
+    h->device = device;
+    if (opts) h->opts = *opts;
+    if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = 0x1p-50;
+    if (h->opts.max_iter <= 0) h->opts.max_iter = 40;
+    if (h->opts.guess != SAKURA_GUESS_ANALYTIC) {
+        delete h;
+        return SAKURA_ENOMODEL;
+    }
+    if (hipSetDevice(device) != hipSuccess ||
+        hipMalloc((void **)&h->cnt, sizeof(DevCounters)) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_cnt, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_out, 12 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        sakura_destroy(h);
+        return SAKURA_EHIP;
+    }
+    *out = h;
+    return SAKURA_OK;
+}
+
+void sakura_destroy(sakura_t *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->state) (void)hipFree(h->state);
+    if (h->part) (void)hipFree(h->part);
+    if (h->scratch_e) (void)hipFree(h->scratch_e);
+    if (h->cnt) (void)hipFree(h->cnt);
+    if (h->host_cnt) (void)hipHostFree(h->host_cnt);
+    if (h->host_out) (void)hipHostFree(h->host_out);
+    delete h;
+}
+
+const char *sakura_last_error(const sakura_t *h) { return h ? h->err.c_str() : "null handle"; }
+
+int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
+                  int64_t nsteps, double G, void *stream, sakura_stats *stats)
+{
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->failed_step = -1;
+    }
+    if (n < 1 || !m || !r || !v) return fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
+    if (n > ((int64_t)1 << 21)) return fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
+    if (!std::isfinite(dt) || !std::isfinite(G) || G < 0.0)
+        return fail(h, SAKURA_EINVAL, "dt and G must be finite and G >= 0");
+    if (nsteps < 0) return fail(h, SAKURA_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return SAKURA_OK;
+
+    SAKURA_HIP(h, hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = (int)((n + TILE - 1) / TILE);
+    const int np = nb * TILE;
+    int rc;
+    if ((rc = grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
+    if ((rc = grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * TILE))) return rc;
+    const bool timing = stats != nullptr;
+    if (timing && (rc = need_events(h, 2 + 2 * (size_t)nsteps))) return rc;
+
+    const double half = 0.5 * dt;
+    const int ntiles = nb * (nb + 1) / 2;
+    const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
+
+    if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
+    k_clear<<<1, 64, 0, st>>>(h->cnt);
+    k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, half, h->state, h->cnt);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * s], st));
+        if (h->opts.histogram)
+            k_pairs<true><<<ntiles, TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
+                                                   h->cnt, kp, s);
+        else
+            k_pairs<false><<<ntiles, TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
+                                                    h->cnt, kp, s);
+        if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * s], st));
+        k_apply<<<nb, 6 * TILE, 0, st>>>((int)n, nb, np, half, h->state, h->part, h->cnt, s);
+    }
+    k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, h->state, r, v, h->cnt);
+    SAKURA_HIP(h, hipGetLastError());
+    if (timing) SAKURA_HIP(h, hipEventRecord(h->events[1], st));
+    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, h->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, st));
+    SAKURA_HIP(h, hipStreamSynchronize(st));
+
+    const DevCounters &c = *h->host_cnt;
+    if (stats) {
+        stats->pair_solves = c.pair_solves;
+        stats->iters_total = c.iters_total;
+        stats->fallbacks = c.fallbacks;
+        stats->iters_max = c.iters_max;
+        for (int k = 0; k < 32; ++k) stats->hist[k] = c.hist[k];
+        stats->pair_launches = nsteps;
+        stats->failed_step = c.status ? c.failed_step : -1;
+        float ms = 0.0f;
+        double tot = 0.0;
+        for (int64_t s = 0; s < nsteps; ++s) {
+            SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[2 + 2 * s], h->events[3 + 2 * s]));
+            tot += ms;
+        }
+        stats->pair_kernel_ms = tot;
+        SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
+        stats->call_ms = ms;
+    }
+    const int code = status_code(c.status);
+    if (code) return fail(h, code, std::string(status_text(code)) + " at step " +
+                                       std::to_string(c.failed_step));
+    return SAKURA_OK;
+}
+
+int sakura_step(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
+                double G, void *stream, sakura_stats *stats)
+{
+    return sakura_evolve(h, n, m, r, v, dt, 1, G, stream, stats);
+}
+
+int sakura_energy(sakura_t *h, int64_t n, const double *m, const double *r, const double *v,
+                  double G, double out[12], void *stream)
+{
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    if (n < 1 || !m || !r || !v || !out) return fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
+    if (n > ((int64_t)1 << 21)) return fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
+    if (!std::isfinite(G)) return fail(h, SAKURA_EINVAL, "G must be finite");
+    SAKURA_HIP(h, hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = (int)((n + TILE - 1) / TILE);
+    const int ntiles = nb * (nb + 1) / 2;
+    int rc;
+    if ((rc = grow(h, &h->scratch_e, &h->cap_e, (int64_t)ntiles + 11 * (int64_t)nb + 12))) return rc;
+    double *tile_u = h->scratch_e, *blk = tile_u + ntiles, *dout = blk + 11 * (size_t)nb;
+    k_energy_pairs<<<ntiles, TILE, 0, st>>>((int)n, nb, m, r, tile_u);
+    k_energy_bodies<<<nb, TILE, 0, st>>>((int)n, m, r, v, blk);
+    k_energy_final<<<1, 64, 0, st>>>(ntiles, nb, G, tile_u, blk, dout);
+    SAKURA_HIP(h, hipGetLastError());
+    SAKURA_HIP(h, hipMemcpyAsync(h->host_out, dout, 12 * sizeof(double), hipMemcpyDeviceToHost, st));
+    SAKURA_HIP(h, hipStreamSynchronize(st));
+    std::memcpy(out, h->host_out, 12 * sizeof(double));
+    return SAKURA_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,167 @@
+"""Python binding of libsakura.so (include/sakura.h): argument marshalling only.
+
+Every step of the integrator runs in the HIP kernels of the library.  torch is
+used for device memory and streams: m, r, v are float64 CUDA tensors of shape
+[n], [n, 3], [n, 3]; r and v are updated in place on the current stream.
+There is no CPU path: if the library is not built, importing raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsakura.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sakura.h")
+
+OK, EINVAL, ENONFINITE, ECOLLIDE, ENOCONV, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -3, -4, -5, -6, -7
+ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ECOLLIDE", -4: "ENOCONV",
+               -5: "EHIP", -6: "ENOMEM", -7: "ENOMODEL"}
+GUESS_ANALYTIC, GUESS_LEARNED = 0, 1
+
+
+class SakuraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("guess", ctypes.c_int), ("kepler_rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("histogram", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("pair_solves", ctypes.c_uint64), ("iters_total", ctypes.c_uint64),
+                ("fallbacks", ctypes.c_uint64), ("iters_max", ctypes.c_uint32),
+                ("hist", ctypes.c_uint32 * 32), ("pair_kernel_ms", ctypes.c_double),
+                ("call_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64),
+                ("failed_step", ctypes.c_int64)]
+
+    def to_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "hist"}
+        d["hist"] = list(self.hist)
+        return d
+
+
+def declared_functions():
+    """Names of the functions include/sakura.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sakura_[a-z_]+)\s*\(", text)))
+
+
+def load_library():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(the Sakura step has no CPU implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.sakura_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(Opts)]
+    L.sakura_create.restype = ctypes.c_int
+    L.sakura_destroy.argtypes = [P]
+    L.sakura_destroy.restype = None
+    L.sakura_step.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
+                              P, ctypes.POINTER(Stats)]
+    L.sakura_step.restype = ctypes.c_int
+    L.sakura_evolve.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int64,
+                                ctypes.c_double, P, ctypes.POINTER(Stats)]
+    L.sakura_evolve.restype = ctypes.c_int
+    L.sakura_energy.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), P]
+    L.sakura_energy.restype = ctypes.c_int
+    L.sakura_last_error.argtypes = [P]
+    L.sakura_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check_state(m, r, v):
+    import torch
+    for name, t in (("m", m), ("r", r), ("v", v)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    n = m.shape[0]
+    if m.dim() != 1 or tuple(r.shape) != (n, 3) or tuple(v.shape) != (n, 3):
+        raise ValueError("shapes must be m [n], r [n, 3], v [n, 3]")
+    if not (m.device == r.device == v.device):
+        raise ValueError("m, r, v must be on one device")
+    return n
+
+
+class Sakura:
+    """A library handle bound to one GPU."""
+
+    def __init__(self, device: int = 0, guess: int = GUESS_ANALYTIC, kepler_rtol: float = 0.0,
+                 max_iter: int = 0, histogram: bool = False):
+        self._lib = lib()
+        self.device = device
+        h = ctypes.c_void_p()
+        o = Opts(guess, kepler_rtol, max_iter, int(bool(histogram)))
+        rc = self._lib.sakura_create(ctypes.byref(h), device, ctypes.byref(o))
+        if rc != OK:
+            raise SakuraError(rc, "sakura_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sakura_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _raise(self, rc):
+        msg = self._lib.sakura_last_error(self._h)
+        raise SakuraError(rc, msg.decode() if msg else "")
+
+    @staticmethod
+    def _stream(t):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+    def evolve(self, m, r, v, dt: float, nsteps: int, G: float = 1.0, stats: bool = False):
+        """nsteps steps of eqs. (27a-d); r, v updated in place.  Returns the
+        stats dict when stats=True."""
+        n = _check_state(m, r, v)
+        st = Stats()
+        rc = self._lib.sakura_evolve(self._h, n, ctypes.c_void_p(m.data_ptr()),
+                                     ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                     float(dt), int(nsteps), float(G), self._stream(m),
+                                     ctypes.byref(st) if stats else None)
+        if rc != OK:
+            self._raise(rc)
+        return st.to_dict() if stats else None
+
+    def step(self, m, r, v, dt: float, G: float = 1.0, stats: bool = False):
+        n = _check_state(m, r, v)
+        st = Stats()
+        rc = self._lib.sakura_step(self._h, n, ctypes.c_void_p(m.data_ptr()),
+                                   ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                   float(dt), float(G), self._stream(m),
+                                   ctypes.byref(st) if stats else None)
+        if rc != OK:
+            self._raise(rc)
+        return st.to_dict() if stats else None
+
+    def energy(self, m, r, v, G: float = 1.0):
+        """{E, K, U, P, L, Rcm} of eqs. (1-3), computed on the GPU."""
+        n = _check_state(m, r, v)
+        out = (ctypes.c_double * 12)()
+        rc = self._lib.sakura_energy(self._h, n, ctypes.c_void_p(m.data_ptr()),
+                                     ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                     float(G), out, self._stream(m))
+        if rc != OK:
+            self._raise(rc)
+        o = list(out)
+        return {"E": o[0], "K": o[1], "U": o[2], "P": o[3:6], "L": o[6:9], "Rcm": o[9:12]}

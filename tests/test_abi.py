@@ -1,0 +1,46 @@
+"""The C-ABI libraries load and export what their headers declare (no GPU)."""
+import ctypes
+import os
+import re
+
+from paper_1402_3325_amd import sakura
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_hip_library_exports_every_declared_symbol():
+    names = sakura.declared_functions()
+    assert {"sakura_create", "sakura_destroy", "sakura_step", "sakura_evolve",
+            "sakura_energy", "sakura_last_error"} <= set(names)
+    L = ctypes.CDLL(sakura.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_stats_struct_matches_header():
+    text = open(sakura.HEADER).read()
+    body = text[text.index("typedef struct {\n    uint64_t pair_solves"):]
+    body = body[:body.index("} sakura_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(\w+)(?:\[\d+\])?;", body)
+    assert fields == [f for f, _ in sakura.Stats._fields_]
+    body = text[text.index("typedef struct {\n    int guess"):]
+    body = re.sub(r"/\*.*?\*/", "", body[:body.index("} sakura_opts;")], flags=re.S)
+    assert re.findall(r"\b(\w+);", body) == [f for f, _ in sakura.Opts._fields_]
+
+
+def test_oracle_library_exports_every_declared_symbol(oracle):
+    text = open(os.path.join(ROOT, "oracle", "sakura_oracle.h")).read()
+    names = sorted(set(re.findall(r"\b(sref_[a-z0-9_]+)\s*\(", text)))
+    L = oracle.lib()
+    assert not [n for n in names if not hasattr(L, n)]
+
+
+def test_product_path_never_loads_the_oracle():
+    """The HIP binding and kernels neither import nor link the oracle."""
+    pkg = os.path.join(ROOT, "paper_1402_3325_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "sref_" not in src, f

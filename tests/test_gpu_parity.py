@@ -1,0 +1,212 @@
+"""GPU (HIP library through the C ABI) vs the CPU oracle, per step from
+identical inputs.
+
+Error metric, for positions (velocities alike):
+    err_r = max_i |r_gpu,i - r_ref,i| / max(|r_ref,i|, r_rms)
+with r_rms the root-mean-square |r| of the input state.  Comparing a single
+step from identical inputs keeps the chaotic growth of differences out of the
+measure.  Tolerance: 1e-12 (relative) on positions and velocities per step.
+"""
+import numpy as np
+import pytest
+
+from paper_1402_3325_amd import workloads
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def lib(torch):
+    from paper_1402_3325_amd.sakura import Sakura
+    h = Sakura(0)
+    yield h
+    h.close()
+
+
+def _dev(torch, *arrays):
+    return [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda") for a in arrays]
+
+
+def gpu_step(torch, lib, m, r, v, tau, G=1.0, nsteps=1, stats=False):
+    mt, rt, vt = _dev(torch, m, r, v)
+    st = lib.evolve(mt, rt, vt, tau, nsteps, G=G, stats=stats)
+    torch.cuda.synchronize()
+    return rt.cpu().numpy(), vt.cpu().numpy(), st
+
+
+def step_error(r_out, v_out, r_ref, v_ref, r_in, v_in):
+    r_rms = np.sqrt(np.mean(np.sum(r_in ** 2, axis=1)))
+    v_rms = np.sqrt(np.mean(np.sum(v_in ** 2, axis=1)))
+    er = np.linalg.norm(r_out - r_ref, axis=1) / np.maximum(np.linalg.norm(r_ref, axis=1), r_rms)
+    ev = np.linalg.norm(v_out - v_ref, axis=1) / np.maximum(np.linalg.norm(v_ref, axis=1), v_rms)
+    return float(er.max()), float(ev.max())
+
+
+def test_parity_planetary_every_step(torch, lib, oracle):
+    """Planetary system (N = 16, tau = P_in/64): 25 consecutive steps, each
+    compared from the oracle's own state."""
+    m, r, v, tau = workloads.planetary(15)
+    worst = (0.0, 0.0)
+    for _ in range(25):
+        rg, vg, _ = gpu_step(torch, lib, m, r, v, tau)
+        ro, vo = oracle.step(m, r, v, tau)
+        e = step_error(rg, vg, ro, vo, r, v)
+        worst = tuple(map(max, worst, e))
+        r, v = ro, vo
+    print("planetary worst err_r, err_v:", worst)
+    assert worst[0] <= TOL and worst[1] <= TOL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 130, 200, 333])
+def test_parity_ragged_sizes(torch, lib, oracle, n):
+    """Sizes below, at and past the 64-particle tile, with ragged tails; a
+    Plummer sphere and a cluster with a central mass and binaries."""
+    rng = np.random.default_rng(1000 + n)
+    cases = [workloads.plummer(n, rng=rng)] if n >= 2 else []
+    if n >= 3:
+        cases.append(workloads.cluster(n_stars=n - 1, rng=rng))
+    if n == 1:
+        cases.append((np.array([0.7]), np.array([[0.1, 0.2, 0.3]]), np.array([[1.0, -2.0, 0.5]]), 0.01))
+    for m, r, v, tau in cases:
+        for dt in (tau, -3.0 * tau):
+            rg, vg, _ = gpu_step(torch, lib, m, r, v, dt)
+            ro, vo = oracle.step(m, r, v, dt)
+            er, ev = step_error(rg, vg, ro, vo, r, v)
+            assert er <= TOL and ev <= TOL, (n, dt, er, ev)
+
+
+def test_parity_plummer_4096_full(torch, lib, oracle):
+    """Equal-mass Plummer N = 4096 (tau = 1/1024): every particle, 3 steps."""
+    m, r, v, tau, _ = workloads.config(1)
+    for _ in range(3):
+        rg, vg, st = gpu_step(torch, lib, m, r, v, tau, stats=True)
+        ro, vo = oracle.step(m, r, v, tau)
+        er, ev = step_error(rg, vg, ro, vo, r, v)
+        print("plummer4096 err", er, ev, "mean iters", st["iters_total"] / st["pair_solves"])
+        assert er <= TOL and ev <= TOL
+        assert st["pair_solves"] == 4096 * 4095 // 2
+        r, v = ro, vo
+
+
+def _cluster_rows(m, rng, count=96):
+    """The central mass, members of tight binaries and random stars."""
+    rows = set([0])
+    rows.update(rng.choice(len(m), count, replace=False).tolist())
+    return np.array(sorted(rows), dtype=np.int64)
+
+
+def test_parity_cluster_16384_sampled(torch, lib, oracle):
+    """Full-size cluster (N = 16384, central mass, 10 % binaries,
+    tau = 1/2048) in the benchmark's launch configuration (sakura_evolve):
+    sampled particles compared with the oracle row by row, over two steps."""
+    m, r, v, tau, _ = workloads.config(2)
+    rng = np.random.default_rng(5)
+    # tightest binaries: the closest neighbours of each other
+    rows = _cluster_rows(m, rng)
+    rin, vin = r, v
+    for step in range(2):
+        rg, vg, st = gpu_step(torch, lib, m, rin, vin, tau, stats=True)
+        assert st["pair_solves"] == 16384 * 16383 // 2
+        ro, vo = oracle.step_rows(m, rin, vin, tau, rows)
+        er, ev = step_error(rg[rows], vg[rows], ro, vo, rin, vin)
+        print("cluster16384 step", step, "err", er, ev, "iters mean",
+              st["iters_total"] / st["pair_solves"], "max", st["iters_max"])
+        assert er <= TOL and ev <= TOL
+        rin, vin = rg, vg
+
+
+def test_massless_particles_exact_orbits_16384(torch, lib):
+    """A central mass and 16383 massless particles: every particle follows its
+    exact Kepler orbit (closed form in long double), at full size."""
+    m, r, v = workloads.test_particles(16384)
+    tau = 0.01
+    rg, vg, _ = gpu_step(torch, lib, m, r, v, tau, nsteps=4)
+    assert np.array_equal(vg[0], v[0]) and np.allclose(rg[0], r[0] + 4 * tau * v[0], atol=0)
+    rng = np.random.default_rng(3)
+    for i in rng.choice(np.arange(1, 16384), 200, replace=False):
+        xr, wr = pins.kepler_elements(4 * tau, m[0], r[i] - r[0], v[i] - v[0])
+        ex = float(np.max(np.abs((rg[i] - rg[0]) - xr))) / np.linalg.norm(r[i])
+        ew = float(np.max(np.abs((vg[i] - vg[0]) - wr))) / np.linalg.norm(v[i])
+        assert ex <= TOL and ew <= TOL, (i, ex, ew)
+
+
+def test_evolve_is_repeated_step_and_deterministic(torch, lib):
+    m, r, v, tau = workloads.plummer(300, rng=np.random.default_rng(77))
+    r5, v5, _ = gpu_step(torch, lib, m, r, v, tau, nsteps=5)
+    r5b, v5b, _ = gpu_step(torch, lib, m, r, v, tau, nsteps=5)
+    assert np.array_equal(r5, r5b) and np.array_equal(v5, v5b)
+    rr, vv = r, v
+    for _ in range(5):
+        rr, vv, _ = gpu_step(torch, lib, m, rr, vv, tau)
+    assert np.array_equal(rr, r5) and np.array_equal(vv, v5)
+
+
+def test_two_body_reversal(torch, lib):
+    m = np.array([0.7, 0.3])
+    r = np.array([[0.3, 0.1, -0.2], [-0.4, 0.2, 0.1]])
+    v = np.array([[0.1, 0.9, 0.0], [-0.3, -1.2, 0.2]])
+    r1, v1, _ = gpu_step(torch, lib, m, r, v, 0.05)
+    r2, v2, _ = gpu_step(torch, lib, m, r1, v1, -0.05)
+    assert np.max(np.abs(r2 - r)) <= 1e-14 and np.max(np.abs(v2 - v)) <= 1e-14
+
+
+def test_massless_system_drifts(torch, lib):
+    rng = np.random.default_rng(4)
+    m = np.zeros(70)
+    r = rng.normal(size=(70, 3))
+    v = rng.normal(size=(70, 3))
+    rg, vg, st = gpu_step(torch, lib, m, r, v, 0.1, stats=True)
+    assert st["pair_solves"] == 0
+    assert np.array_equal(vg, v)
+    assert np.allclose(rg, r + 0.1 * v, rtol=0, atol=1e-15)
+
+
+def test_errors_leave_state_unchanged(torch, lib):
+    from paper_1402_3325_amd.sakura import SakuraError, ECOLLIDE, ENONFINITE, EINVAL
+    m, r, v, tau = workloads.plummer(100, rng=np.random.default_rng(2))
+    bad = {}
+    rc = r.copy()
+    rc[17] = rc[3]
+    vc = v.copy()
+    vc[17] = vc[3]
+    bad[ECOLLIDE] = (m, rc, vc)
+    rn = r.copy()
+    rn[50, 1] = np.nan
+    bad[ENONFINITE] = (m, rn, v)
+    mn = m.copy()
+    mn[9] = -1.0
+    bad[EINVAL] = (mn, r, v)
+    for code, (mm, rr, vv) in bad.items():
+        mt, rt, vt = _dev(torch, mm, rr, vv)
+        with pytest.raises(SakuraError) as e:
+            lib.evolve(mt, rt, vt, tau, 3)
+        assert e.value.code == code
+        out_r, out_v = rt.cpu().numpy(), vt.cpu().numpy()
+        assert np.array_equal(out_r, rr, equal_nan=True) and np.array_equal(out_v, vv)
+    mt, rt, vt = _dev(torch, m, r, v)
+    with pytest.raises(SakuraError):
+        lib.evolve(mt, rt, vt, float("nan"), 1)
+    # the handle still works after errors
+    lib.evolve(mt, rt, vt, tau, 1)
+
+
+def test_energy_matches_oracle(torch, lib, oracle):
+    for k in (0, 1):
+        m, r, v, tau, _ = workloads.config(k)
+        mt, rt, vt = _dev(torch, m, r, v)
+        eg = lib.energy(mt, rt, vt)
+        eo = oracle.energy(m, r, v)
+        assert abs(eg["E"] - eo["E"]) <= 1e-13 * abs(eo["U"])
+        assert abs(eg["K"] - eo["K"]) <= 1e-14 * eo["K"]
+        for key in ("P", "L", "Rcm"):
+            assert np.max(np.abs(np.array(eg[key]) - eo[key])) <= 1e-14 * (1 + np.abs(eo[key]).max())
