@@ -81,7 +81,19 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with HBM bytes per pair launch from rocprofv3 counters")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (x4), to scale "
+                         "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "launches": 4}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus N > 1 is not supported",
               file=sys.stderr)
