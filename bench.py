@@ -25,11 +25,37 @@ METRIC = "Kepler pair-solves/s at N=16384 (FP64), learned-guess vs plain at 1e-1
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
 # Algorithmic FP64 operations per pair solve, counted in the kernel source
-# (add/sub/mul/div/sqrt = 1, fma = 2): pair setup and back-drift 19, Kepler
-# set-up and starter 38, one Laguerre iteration 63, Lagrange coefficients 12,
-# increments, weights and the two-sided sums 49.
-FLOPS_FIXED = 19 + 38 + 12 + 49
-FLOPS_PER_ITER = 63
+# (add/sub/mul and the hardware reciprocal / reciprocal-square-root estimates
+# = 1, fma = 2): pair set-up and back-drift 19, Kepler set-up and starter 47,
+# Taylor shift of the G-functions 28, Lagrange coefficients 19, increments,
+# weights and the two-sided sums 57; each evaluation of the Kepler equation
+# with its Laguerre step 72 plus the convergence estimate 18.
+FLOPS_FIXED = 19 + 47 + 28 + 19 + 57
+FLOPS_PER_ITER = 72 + 18
+KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
+                  "paper_1402_3325_amd/csrc/common.hpp",
+                  "paper_1402_3325_amd/csrc/sakura.hip"]
+TRAFFIC_FILE = "profiles/k_pairs_cluster16384.traffic.json"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counters,
+    or None when the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["bytes_per_launch"]
 
 
 def flops_per_pair(mean_iters):
@@ -79,8 +105,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with HBM bytes per pair launch from rocprofv3 counters")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (x4), to scale "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -127,9 +151,7 @@ def main():
     pair_ms = st["pair_kernel_ms"] / max(st["pair_launches"], 1)
     fl = flops_per_pair(k_mean) * pairs
     achieved = fl / (pair_ms * 1e-3) / 1e12
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = measured_traffic()
 
     out = {
         "metric": METRIC,
@@ -156,6 +178,7 @@ def main():
         "max_kepler_iters": st["iters_max"],
         "fallbacks": st["fallbacks"],
         "flops_per_pair": flops_per_pair(k_mean),
+        "kernel_source_hash": kernel_source_hash(),
         "err_vs_oracle": parity,
     }
     if not args.no_cpu_baseline:

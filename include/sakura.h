@@ -93,6 +93,32 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                   double dt, int64_t nsteps, double G, void *stream,
                   sakura_stats *stats);
 
+/* Batched ensembles: nsys independent systems, each of 1..64 particles, stored
+ * back to back (CSR): system s owns particles offsets[s] .. offsets[s+1]-1 of
+ * m, r, v.  offsets is a HOST array of nsys + 1 entries with offsets[0] = 0;
+ * dt is a DEVICE array of nsys per-system steps.  Every system takes nsteps
+ * steps of eqs. (27a-d) inside one persistent kernel (the launch sequence is
+ * captured in a hipGraph and replayed while the arguments are unchanged).
+ * Systems do not interact.  On any error no system is updated. */
+int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
+                        double *r, double *v, const double *dt, int64_t nsteps, double G,
+                        void *stream, sakura_stats *stats);
+
+/* Packing of batched systems: policy 0 gives a system of n particles n lanes
+ * (dense), 1 rounds n up to even, 2 to a power of two; waves_per_cu sizes the
+ * persistent grid; use_graph = 0 launches the kernels directly. */
+int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_graph);
+
+/* Lanes used by systems of exactly n particles (n <= lanes <= 64). */
+int sakura_batch_set_group(sakura_t *h, int n, int lanes);
+
+/* Time every packing policy and grid size on this ensemble for probe_steps
+ * steps (on scratch copies; r and v are not modified), keep the fastest on the
+ * handle and report its time in *best_ms (may be NULL). */
+int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
+                          const double *r, const double *v, const double *dt,
+                          int64_t probe_steps, double G, void *stream, double *best_ms);
+
 /* Energy diagnostics of eqs. (1-3) with compensated sums:
  * out[12] (HOST) = {E, K, U, P[3], L[3], Rcm[3]}: total, kinetic and potential
  * energy, linear and angular momentum, centre of mass. */

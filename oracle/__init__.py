@@ -53,6 +53,8 @@ def lib():
                                   ctypes.c_int64, ctypes.c_double, ctypes.c_int]
         L.sref_energy.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]
         L.sref_num_threads.restype = ctypes.c_int
+        L.sref_mlp_forward.argtypes = [_D, ctypes.c_int64, _D, _D]
+        L.sref_mlp_loss_grad.argtypes = [_D, ctypes.c_int64, _D, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -161,3 +163,30 @@ def energy(m, r, v, G=1.0):
 
 def num_threads():
     return lib().sref_num_threads()
+
+
+MLP_PARAMS = 4801
+
+
+def mlp_forward(params, x):
+    """Reference forward pass of the learned-starter network (fp64)."""
+    p = _f64(params, (MLP_PARAMS,))
+    x = _f64(x).reshape(-1, 8)
+    out = np.empty(x.shape[0])
+    rc = lib().sref_mlp_forward(_p(p), x.shape[0], _p(x), _p(out))
+    if rc:
+        raise OracleError(rc, "sref_mlp_forward")
+    return out
+
+
+def mlp_loss_grad(params, x, y):
+    """Mean squared error and its gradient (fp64)."""
+    p = _f64(params, (MLP_PARAMS,))
+    x = _f64(x).reshape(-1, 8)
+    y = _f64(y, (x.shape[0],))
+    loss = np.empty(1)
+    grad = np.empty(MLP_PARAMS)
+    rc = lib().sref_mlp_loss_grad(_p(p), x.shape[0], _p(x), _p(y), _p(loss), _p(grad))
+    if rc:
+        raise OracleError(rc, "sref_mlp_loss_grad")
+    return float(loss[0]), grad

@@ -477,6 +477,88 @@ int sref_energy(int64_t n, const double *m, const double *r, const double *v,
     return SREF_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Learned-starter network reference: plain loops in fp64, written from the  */
+/* definition of a two-hidden-layer perceptron and the chain rule.           */
+/* ------------------------------------------------------------------------ */
+enum { MLP_IN = 8, MLP_H = 64 };
+#define MLP_OFF_W1 0
+#define MLP_OFF_B1 (MLP_OFF_W1 + MLP_H * MLP_IN)
+#define MLP_OFF_W2 (MLP_OFF_B1 + MLP_H)
+#define MLP_OFF_B2 (MLP_OFF_W2 + MLP_H * MLP_H)
+#define MLP_OFF_W3 (MLP_OFF_B2 + MLP_H)
+#define MLP_OFF_B3 (MLP_OFF_W3 + MLP_H)
+
+static double mlp_one(const double *p, const double *x, double *z1, double *a1,
+                      double *z2, double *a2)
+{
+    const double *W1 = p + MLP_OFF_W1, *b1 = p + MLP_OFF_B1;
+    const double *W2 = p + MLP_OFF_W2, *b2 = p + MLP_OFF_B2;
+    const double *W3 = p + MLP_OFF_W3, *b3 = p + MLP_OFF_B3;
+    for (int i = 0; i < MLP_H; ++i) {
+        double z = b1[i];
+        for (int j = 0; j < MLP_IN; ++j) z += W1[i * MLP_IN + j] * x[j];
+        z1[i] = z;
+        a1[i] = z > 0.0 ? z : 0.0;
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+        double z = b2[i];
+        for (int j = 0; j < MLP_H; ++j) z += W2[i * MLP_H + j] * a1[j];
+        z2[i] = z;
+        a2[i] = z > 0.0 ? z : 0.0;
+    }
+    double o = b3[0];
+    for (int j = 0; j < MLP_H; ++j) o += W3[j] * a2[j];
+    return o;
+}
+
+int sref_mlp_forward(const double *params, int64_t batch, const double *x, double *out)
+{
+    if (!params || !x || !out || batch < 0) return SREF_EINVAL;
+    for (int64_t b = 0; b < batch; ++b) {
+        double z1[MLP_H], a1[MLP_H], z2[MLP_H], a2[MLP_H];
+        out[b] = mlp_one(params, x + MLP_IN * b, z1, a1, z2, a2);
+    }
+    return SREF_OK;
+}
+
+int sref_mlp_loss_grad(const double *params, int64_t batch, const double *x,
+                       const double *y, double *loss, double *grad)
+{
+    if (!params || !x || !y || !loss || !grad || batch < 1) return SREF_EINVAL;
+    const double *W2 = params + MLP_OFF_W2, *W3 = params + MLP_OFF_W3;
+    memset(grad, 0, sizeof(double) * SREF_MLP_PARAMS);
+    double L = 0.0;
+    for (int64_t b = 0; b < batch; ++b) {
+        const double *xb = x + MLP_IN * b;
+        double z1[MLP_H], a1[MLP_H], z2[MLP_H], a2[MLP_H], d2[MLP_H], d1[MLP_H];
+        const double o = mlp_one(params, xb, z1, a1, z2, a2);
+        const double e = o - y[b];
+        L += e * e;
+        const double g = 2.0 * e / (double)batch; /* dL/do */
+        grad[MLP_OFF_B3] += g;
+        for (int j = 0; j < MLP_H; ++j) {
+            grad[MLP_OFF_W3 + j] += g * a2[j];
+            d2[j] = z2[j] > 0.0 ? g * W3[j] : 0.0; /* dL/dz2 */
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            grad[MLP_OFF_B2 + i] += d2[i];
+            for (int j = 0; j < MLP_H; ++j) grad[MLP_OFF_W2 + i * MLP_H + j] += d2[i] * a1[j];
+        }
+        for (int j = 0; j < MLP_H; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < MLP_H; ++i) s += W2[i * MLP_H + j] * d2[i];
+            d1[j] = z1[j] > 0.0 ? s : 0.0; /* dL/dz1 */
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            grad[MLP_OFF_B1 + i] += d1[i];
+            for (int j = 0; j < MLP_IN; ++j) grad[MLP_OFF_W1 + i * MLP_IN + j] += d1[i] * xb[j];
+        }
+    }
+    *loss = L / (double)batch;
+    return SREF_OK;
+}
+
 int sref_num_threads(void)
 {
 #ifdef _OPENMP

@@ -69,6 +69,17 @@ int sref_evolve(int64_t n, const double *m, double *r, double *v, double tau,
 int sref_energy(int64_t n, const double *m, const double *r, const double *v,
                 double G, double out[12]);
 
+/* Reference of the learned Kepler starter network (an extension of the
+ * method, not in the paper): 8 -> 64 -> 64 -> 1, ReLU, parameters packed as
+ * W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values).
+ * sref_mlp_forward: out[b] for inputs x[b][8].
+ * sref_mlp_loss_grad: mean squared error over the batch and its gradient
+ * with respect to every parameter (same packing). */
+#define SREF_MLP_PARAMS 4801
+int sref_mlp_forward(const double *params, int64_t batch, const double *x, double *out);
+int sref_mlp_loss_grad(const double *params, int64_t batch, const double *x,
+                       const double *y, double *loss, double *grad);
+
 /* Number of OpenMP threads the row loops use. */
 int sref_num_threads(void);
 

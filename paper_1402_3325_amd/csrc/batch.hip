@@ -1,0 +1,400 @@
+// Batched ensembles: many independent small systems (n <= 64 each) advanced
+// for all steps inside one persistent kernel.
+//
+// Each system is handled by a group of L lanes (L >= n, chosen per system size
+// by a policy table that sakura_autotune_batch can tune); a wavefront holds
+// floor(64 / L) systems of equal size.  Within a group the pairs follow the
+// same diagonal schedule as the tile kernel: in sub-step s lane l meets slot
+// (l + s) mod L, s = 1 .. floor((L - 1) / 2) plus, for even L, s = L/2 on the
+// lower half of the lanes, which visits each unordered pair once.  The
+// particle state stays in registers for all steps; positions, velocities and
+// masses of the current step are published to LDS for the partners and the
+// j-side sums are accumulated in LDS slots that no two lanes share within a
+// sub-step.
+//
+// Work items (groups of systems) are sorted by cost, largest first, and popped
+// from an atomic counter by a persistent grid; every wave exits once the queue
+// is empty.
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace {
+using namespace sk;
+
+struct WorkItem {
+    int first; // index into the sorted system order
+    int count; // systems in this item
+    int L;     // lanes per system
+    int pad;
+};
+
+__global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__restrict__ items,
+                                                const int *__restrict__ order,
+                                                const int64_t *__restrict__ offsets,
+                                                const double *__restrict__ m,
+                                                const double *__restrict__ r,
+                                                const double *__restrict__ v,
+                                                const double *__restrict__ dt,
+                                                double *__restrict__ staged, int64_t ntot,
+                                                long long nsteps,
+                                                double G, DevCounters *cnt, SlotStats *slots,
+                                                kep::KeplerParams kp)
+{
+    __shared__ double sj[7][TILE]; // x y z vx vy vz m of every lane this step
+    __shared__ double sa[6][TILE]; // j-side sums
+    const int lane = threadIdx.x;
+    unsigned n_solve = 0, it_sum = 0, it_max = 0, n_fb = 0;
+
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(&cnt->work_next, 1u);
+        item = __shfl(item, 0, 64);
+        if (item >= nitems) break;
+        const WorkItem w = items[item];
+        const int L = w.L;
+        const int g = lane / L, l = lane - g * L;
+        const bool lane_in_tile = g < TILE / L; // lanes past the last full group idle
+        const bool in_group = g < w.count && lane_in_tile;
+        const int sys = in_group ? order[w.first + g] : 0;
+        const int64_t off = in_group ? offsets[sys] : 0;
+        const int nsys_n = in_group ? (int)(offsets[sys + 1] - off) : 0;
+        const bool valid = in_group && l < nsys_n;
+        const double tau = in_group ? dt[sys] : 0.0;
+        const double h = 0.5 * tau;
+        const int64_t p = off + l;
+        double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+            mi = m[p];
+            for (int c = 0; c < 3; ++c) {
+                x[c] = r[3 * p + c];
+                u[c] = v[3 * p + c];
+            }
+            bool fin = isfinite(mi) && isfinite(tau);
+            for (int c = 0; c < 3; ++c) fin = fin && isfinite(x[c]) && isfinite(u[c]);
+            if (!fin) record_error(cnt, ST_NONFINITE, 0);
+            else if (!(mi >= 0.0)) record_error(cnt, ST_INVAL, 0);
+        }
+        const int nsub = (L - 1) / 2 + ((L & 1) ? 0 : 1);
+        unsigned flags = 0;
+
+        for (long long step = 0; step < nsteps; ++step) {
+            double xh[3];
+            for (int c = 0; c < 3; ++c) xh[c] = x[c] + h * u[c]; // (27a)
+            __syncthreads(); // the previous step's readers are done
+            sj[0][lane] = xh[0];
+            sj[1][lane] = xh[1];
+            sj[2][lane] = xh[2];
+            sj[3][lane] = u[0];
+            sj[4][lane] = u[1];
+            sj[5][lane] = u[2];
+            sj[6][lane] = valid ? mi : 0.0;
+            for (int c = 0; c < 6; ++c) sa[c][lane] = 0.0;
+            __syncthreads();
+
+            double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int s = 1; s <= nsub; ++s) {
+                int ql = l + s;
+                ql = ql >= L ? ql - L : ql;
+                const int q = lane_in_tile ? g * L + ql : lane; // always inside [0, 64)
+                const double mj = sj[6][q];
+                const double msum = mi + mj;
+                const bool act = valid && ql < nsys_n && msum > 0.0 &&
+                                 !((L & 1) == 0 && 2 * s == L && 2 * l >= L);
+                const double w0 = u[0] - sj[3][q], w1 = u[1] - sj[4][q], w2 = u[2] - sj[5][q];
+                const double x0 = fma(-h, w0, xh[0] - sj[0][q]);
+                const double x1 = fma(-h, w1, xh[1] - sj[1][q]);
+                const double x2 = fma(-h, w2, xh[2] - sj[2][q]);
+                const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+                const bool collide = act && !(r0sq > 0.0);
+                const bool live = act && !collide;
+                const kep::PairFlow f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0,
+                                                         x0, x1, x2, w0, w1, w2,
+                                                         live ? r0sq : 1.0, kp);
+                const double a = fma(-h, f.fdot, f.fm1);
+                const double b = fma(-h, f.gdm1, f.gmt);
+                const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
+                                     fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
+                                     fma(f.fdot, x2, f.gdm1 * w2)};
+                const double inv = live ? kep::rcp_refined(msum) : 0.0;
+                const double wgt_i = mj * inv, wgt_j = mi * inv;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    acc[c] = fma(wgt_i, d[c], acc[c]);
+                    sa[c][q] = fma(-wgt_j, d[c], sa[c][q]);
+                }
+                if (live) {
+                    ++n_solve;
+                    it_sum += f.iters;
+                    it_max = max(it_max, (unsigned)f.iters);
+                    n_fb += f.safeguarded ? 1u : 0u;
+                    if (!f.converged) flags |= ST_NOCONV;
+                }
+                if (collide) flags |= ST_COLLIDE;
+                __syncthreads(); // j-side sums of this sub-step visible to the next
+            }
+            bool fin = true;
+            for (int c = 0; c < 3; ++c) {
+                const double rt = xh[c] + (acc[c] + sa[c][lane]);        // (27b)
+                const double v1 = u[c] + (acc[3 + c] + sa[3 + c][lane]); // (27c)
+                x[c] = rt + h * v1;                                      // (27d)
+                u[c] = v1;
+                fin = fin && isfinite(x[c]) && isfinite(v1);
+            }
+            if (valid && !fin) flags |= ST_NONFINITE;
+            if (flags) record_error(cnt, flags, step);
+            flags = 0;
+        }
+        if (valid) {
+            for (int c = 0; c < 3; ++c) {
+                staged[3 * p + c] = x[c];
+                staged[3 * (ntot + p) + c] = u[c];
+            }
+        }
+    }
+    n_solve = wave_sum(n_solve);
+    it_sum = wave_sum(it_sum);
+    n_fb = wave_sum(n_fb);
+    it_max = wave_max(it_max);
+    if (lane == 0) slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+}
+
+// Staged results -> caller arrays, only when every system and step succeeded.
+__global__ void k_batch_export(int64_t ntot, const double *__restrict__ staged,
+                               double *__restrict__ r, double *__restrict__ v,
+                               const DevCounters *cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * ntot || cnt->status) return;
+    r[i] = staged[i];
+    v[i] = staged[3 * ntot + i];
+}
+
+} // namespace
+
+namespace {
+
+// Lanes per system of size n under each packing policy: 0 dense (n lanes),
+// 1 even (n rounded up to even), 2 power of two.
+int policy_group(int policy, int n)
+{
+    switch (policy) {
+    case 1: return n + (n & 1);                // even group
+    case 2: {                                  // power of two
+        int L = 1;
+        while (L < n) L <<= 1;
+        return L;
+    }
+    default: return n;                         // dense
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
+                        double *r, double *v, const double *dt, int64_t nsteps, double G,
+                        void *stream, sakura_stats *stats)
+{
+    using namespace sk;
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->failed_step = -1;
+    }
+    if (nsys < 1 || !offsets || !m || !r || !v || !dt)
+        return fail(h, SAKURA_EINVAL, "nsys < 1 or null pointer");
+    if (nsys > (1 << 26)) return fail(h, SAKURA_EINVAL, "too many systems");
+    if (!std::isfinite(G) || G < 0.0) return fail(h, SAKURA_EINVAL, "G must be finite and >= 0");
+    if (nsteps < 0) return fail(h, SAKURA_EINVAL, "nsteps < 0");
+    if (offsets[0] != 0) return fail(h, SAKURA_EINVAL, "offsets[0] must be 0");
+    for (int64_t s = 0; s < nsys; ++s) {
+        const int64_t ns = offsets[s + 1] - offsets[s];
+        if (ns < 1 || ns > TILE)
+            return fail(h, SAKURA_EINVAL, "system " + std::to_string(s) + " has " +
+                                              std::to_string(ns) +
+                                              " particles; batched systems hold 1..64");
+    }
+    if (nsteps == 0) return SAKURA_OK;
+    const int64_t ntot = offsets[nsys];
+
+    // Work items: systems sorted by size (largest first), equal sizes packed
+    // floor(64 / L) to a wavefront.
+    std::vector<int> order((size_t)nsys);
+    for (int64_t s = 0; s < nsys; ++s) order[(size_t)s] = (int)s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+    });
+    std::vector<int> items; // 4 ints per item
+    for (size_t k = 0; k < order.size();) {
+        const int n = (int)(offsets[order[k] + 1] - offsets[order[k]]);
+        const int L = std::max(n, std::min(TILE, h->batch_group[n]));
+        const int per = TILE / L;
+        size_t e = k;
+        while (e < order.size() && e - k < (size_t)per &&
+               offsets[order[e] + 1] - offsets[order[e]] == n)
+            ++e;
+        items.push_back((int)k);
+        items.push_back((int)(e - k));
+        items.push_back(L);
+        items.push_back(0);
+        k = e;
+    }
+    const int nitems = (int)(items.size() / 4);
+    h->host_work.assign(items.begin(), items.end());
+    h->host_work.insert(h->host_work.end(), order.begin(), order.end());
+
+    SAKURA_HIP(h, hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if ((rc = grow(h, &h->batch_state, &h->cap_batch, 6 * ntot))) return rc;
+    if ((rc = grow(h, &h->batch_work, &h->cap_work, (int64_t)h->host_work.size()))) return rc;
+    if ((rc = grow(h, &h->batch_offsets, &h->cap_offsets, nsys + 1))) return rc;
+    SAKURA_HIP(h, hipMemcpyAsync(h->batch_work, h->host_work.data(),
+                                 h->host_work.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    SAKURA_HIP(h, hipMemcpyAsync(h->batch_offsets, offsets, (size_t)(nsys + 1) * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, st));
+    const bool timing = stats != nullptr;
+    if (timing) {
+        while (h->events.size() < 2) {
+            hipEvent_t e;
+            SAKURA_HIP(h, hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+    }
+
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int grid = std::max(1, std::min(nitems, cus * std::max(1, h->batch_waves_per_cu)));
+    const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
+    const WorkItem *witems = reinterpret_cast<const WorkItem *>(h->batch_work);
+    const int *worder = h->batch_work + 4 * nitems;
+    const unsigned eblocks = (unsigned)((3 * ntot + 255) / 256);
+
+    // The launch sequence is captured once into a graph (on a private stream)
+    // and replayed while the arguments stay the same.
+    char keybuf[512];
+    std::snprintf(keybuf, sizeof(keybuf), "%p %p %p %p %p %p %lld %lld %a %d %d %a %d",
+                  (const void *)m, (void *)r, (void *)v, (const void *)dt,
+                  (void *)h->batch_state, (void *)h->batch_work, (long long)nsys,
+                  (long long)nsteps, G, nitems, grid, kp.tol, kp.max_iter);
+    const bool use_graph = !h->batch_no_graph;
+    if (use_graph && (h->graph_exec == nullptr || h->graph_key != keybuf)) {
+        if (h->graph_exec) {
+            (void)hipGraphExecDestroy(h->graph_exec);
+            h->graph_exec = nullptr;
+        }
+        if (h->graph) {
+            (void)hipGraphDestroy(h->graph);
+            h->graph = nullptr;
+        }
+        if (!h->capture_stream)
+            SAKURA_HIP(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+        SAKURA_HIP(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+        k_clear<<<1, NSLOT, 0, h->capture_stream>>>(h->cnt, h->slots);
+        k_batch<<<grid, TILE, 0, h->capture_stream>>>(nitems, witems, worder, h->batch_offsets, m,
+                                                      r, v, dt, h->batch_state, ntot,
+                                                      (long long)nsteps, G, h->cnt, h->slots, kp);
+        k_batch_export<<<eblocks, 256, 0, h->capture_stream>>>(ntot, h->batch_state, r, v,
+                                                               h->cnt);
+        k_fold_stats<<<1, NSLOT, 0, h->capture_stream>>>(h->slots, h->cnt);
+        SAKURA_HIP(h, hipStreamEndCapture(h->capture_stream, &h->graph));
+        SAKURA_HIP(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+        h->graph_key = keybuf;
+    }
+    if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
+    if (use_graph) {
+        SAKURA_HIP(h, hipGraphLaunch(h->graph_exec, st));
+    } else {
+        k_clear<<<1, NSLOT, 0, st>>>(h->cnt, h->slots);
+        k_batch<<<grid, TILE, 0, st>>>(nitems, witems, worder, h->batch_offsets, m, r, v, dt,
+                                       h->batch_state, ntot, (long long)nsteps, G, h->cnt,
+                                       h->slots, kp);
+        k_batch_export<<<eblocks, 256, 0, st>>>(ntot, h->batch_state, r, v, h->cnt);
+        k_fold_stats<<<1, NSLOT, 0, st>>>(h->slots, h->cnt);
+        SAKURA_HIP(h, hipGetLastError());
+    }
+    if (timing) SAKURA_HIP(h, hipEventRecord(h->events[1], st));
+    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, h->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, st));
+    SAKURA_HIP(h, hipStreamSynchronize(st));
+
+    const DevCounters &c = *h->host_cnt;
+    if (stats) {
+        stats->pair_solves = c.pair_solves;
+        stats->iters_total = c.iters_total;
+        stats->fallbacks = c.fallbacks;
+        stats->iters_max = c.iters_max;
+        stats->pair_launches = 1;
+        stats->failed_step = c.status ? c.failed_step : -1;
+        float ms = 0.0f;
+        SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
+        stats->call_ms = ms;
+        stats->pair_kernel_ms = ms;
+    }
+    const int code = status_code(c.status);
+    if (code) return fail(h, code, std::string(status_text(code)) + " at step " +
+                                       std::to_string(c.failed_step));
+    return SAKURA_OK;
+}
+
+int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_graph)
+{
+    if (!h || policy < 0 || policy > 2 || waves_per_cu < 1 || waves_per_cu > 32)
+        return SAKURA_EINVAL;
+    for (int n = 1; n <= sk::TILE; ++n) h->batch_group[n] = policy_group(policy, n);
+    h->batch_waves_per_cu = waves_per_cu;
+    h->batch_no_graph = !use_graph;
+    return SAKURA_OK;
+}
+
+int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
+                          const double *r, const double *v, const double *dt,
+                          int64_t probe_steps, double G, void *stream, double *best_ms)
+{
+    using namespace sk;
+    if (!h || nsys < 1 || !offsets || probe_steps < 1) return SAKURA_EINVAL;
+    const int64_t ntot = offsets[nsys];
+    int rc;
+    if ((rc = grow(h, &h->tune_rv, &h->cap_tune, 6 * ntot))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int waves[3] = {4, 8, 16};
+    double best = 1e300;
+    int best_policy = 0, best_waves = 8;
+    const int keep_graph = !h->batch_no_graph;
+    for (int policy = 0; policy < 3; ++policy) {
+        for (int wi = 0; wi < 3; ++wi) {
+            sakura_batch_set_policy(h, policy, waves[wi], 0);
+            double t = 0.0;
+            for (int rep = 0; rep < 2; ++rep) { // first run warms up
+                SAKURA_HIP(h, hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
+                                             hipMemcpyDeviceToDevice, st));
+                SAKURA_HIP(h, hipMemcpyAsync(h->tune_rv + 3 * ntot, v, 3 * ntot * sizeof(double),
+                                             hipMemcpyDeviceToDevice, st));
+                sakura_stats s;
+                rc = sakura_batch_evolve(h, nsys, offsets, m, h->tune_rv, h->tune_rv + 3 * ntot,
+                                         dt, probe_steps, G, stream, &s);
+                if (rc) return rc;
+                t = s.call_ms;
+            }
+            if (t < best) {
+                best = t;
+                best_policy = policy;
+                best_waves = waves[wi];
+            }
+        }
+    }
+    sakura_batch_set_policy(h, best_policy, best_waves, keep_graph);
+    if (best_ms) *best_ms = best;
+    return SAKURA_OK;
+}
+
+int sakura_batch_set_group(sakura_t *h, int n, int lanes)
+{
+    if (!h || n < 1 || n > sk::TILE || lanes < n || lanes > sk::TILE) return SAKURA_EINVAL;
+    h->batch_group[n] = lanes;
+    return SAKURA_OK;
+}
+
+} // extern "C"

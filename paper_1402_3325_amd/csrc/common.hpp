@@ -1,0 +1,175 @@
+// Shared declarations of the Sakura HIP library: status bits and device
+// counters, wavefront helpers, the handle and host-side helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sakura.h"
+#include "kepler_device.hpp"
+
+namespace sk {
+
+constexpr int TILE = 64; // particles per block = lanes per wavefront
+
+enum : unsigned { ST_NONFINITE = 1u, ST_COLLIDE = 2u, ST_NOCONV = 4u, ST_INVAL = 8u };
+
+struct DevCounters {
+    unsigned status; // ST_* bits
+    unsigned iters_max;
+    unsigned long long pair_solves;
+    unsigned long long iters_total;
+    unsigned long long fallbacks;
+    long long failed_step;
+    unsigned hist[32];
+    unsigned work_next; // work-queue head of the batched kernel
+};
+
+// Iteration statistics are added into NSLOT counter slots of one cache line
+// each (slot = workgroup index mod NSLOT), so that tens of thousands of
+// wavefronts never serialise on one address; k_fold_stats sums the slots.
+constexpr int NSLOT = 1024;
+struct SlotStats {
+    unsigned long long pair_solves, iters_total, fallbacks;
+    unsigned iters_max;
+    unsigned pad[9];
+};
+static_assert(sizeof(SlotStats) == 64, "one cache line per slot");
+
+__device__ inline void slot_add(SlotStats *slots, unsigned block, unsigned long long solves,
+                                unsigned long long iters, unsigned long long fb, unsigned imax)
+{
+    SlotStats *sl = slots + (block & (NSLOT - 1));
+    atomicAdd(&sl->pair_solves, solves);
+    atomicAdd(&sl->iters_total, iters);
+    atomicAdd(&sl->fallbacks, fb);
+    atomicMax(&sl->iters_max, imax);
+}
+
+__device__ inline unsigned wave_sum(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline unsigned wave_max(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = max(x, (unsigned)__shfl_xor(x, o, 64));
+    return x;
+}
+__device__ inline unsigned wave_or(unsigned x)
+{
+    for (int o = 32; o > 0; o >>= 1) x |= (unsigned)__shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline double wave_sum_d(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ inline void record_error(DevCounters *c, unsigned bits, long long step)
+{
+    atomicOr(&c->status, bits);
+    atomicMin(&c->failed_step, step);
+}
+
+__global__ void k_clear(DevCounters *c, SlotStats *slots);
+__global__ void k_fold_stats(const SlotStats *slots, DevCounters *c);
+
+} // namespace sk
+
+struct sakura {
+    int device = 0;
+    sakura_opts opts{};
+    std::string err;
+    double *state = nullptr; // [10][np]
+    int64_t cap_np = 0;
+    double *part = nullptr; // [nb][nb][6][64]
+    int64_t cap_part = 0;
+    double *scratch_e = nullptr; // energy partials
+    int64_t cap_e = 0;
+    sk::DevCounters *cnt = nullptr;
+    sk::SlotStats *slots = nullptr;
+    sk::DevCounters *host_cnt = nullptr; // pinned
+    double *host_out = nullptr;          // pinned, 12 doubles
+    std::vector<hipEvent_t> events;
+    // batched ensembles
+    double *batch_state = nullptr; // staged r, v of all systems
+    int64_t cap_batch = 0;
+    int *batch_work = nullptr; // work items and the sorted system order
+    int64_t cap_work = 0;
+    int64_t *batch_offsets = nullptr;
+    int64_t cap_offsets = 0;
+    std::vector<int> host_work;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::string graph_key;
+    int batch_group[65] = {0}; // lanes per system of each size (0: the size itself)
+    double *tune_rv = nullptr; // autotuner scratch copies of r, v
+    int64_t cap_tune = 0;
+    int batch_waves_per_cu = 8;
+    int batch_no_graph = 0;
+};
+
+namespace sk {
+
+inline int fail(sakura_t *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define SAKURA_HIP(h, call)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return sk::fail((h), SAKURA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int grow(sakura_t *h, T **buf, int64_t *cap, int64_t need)
+{
+    if (*cap >= need) return SAKURA_OK;
+    if (*buf) {
+        SAKURA_HIP(h, hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    if (hipMalloc((void **)buf, (size_t)need * sizeof(T)) != hipSuccess) {
+        *buf = nullptr;
+        return fail(h, SAKURA_ENOMEM, "device allocation of " +
+                                          std::to_string((size_t)need * sizeof(T)) +
+                                          " bytes failed");
+    }
+    *cap = need;
+    return SAKURA_OK;
+}
+
+inline int status_code(unsigned st)
+{
+    if (st & ST_INVAL) return SAKURA_EINVAL;
+    if (st & ST_NONFINITE) return SAKURA_ENONFINITE;
+    if (st & ST_COLLIDE) return SAKURA_ECOLLIDE;
+    if (st & ST_NOCONV) return SAKURA_ENOCONV;
+    return SAKURA_OK;
+}
+
+inline const char *status_text(int code)
+{
+    switch (code) {
+    case SAKURA_EINVAL: return "negative mass";
+    case SAKURA_ENONFINITE: return "non-finite position, velocity or mass";
+    case SAKURA_ECOLLIDE: return "two particles at zero separation (no softening)";
+    case SAKURA_ENOCONV: return "a Kepler solve did not converge";
+    default: return "";
+    }
+}
+
+} // namespace sk

@@ -72,6 +72,38 @@ SAKURA_HD inline void stumpff23(double z, double &c2, double &c3)
     }
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64 / v_rsq_f64, relative error near 2^-23) refined by Newton steps:
+// one step gives about 2^-46, two steps the last-bit accuracy of a division.
+SAKURA_HD inline double rcp_refined(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+SAKURA_HD inline double rcp_step(double x) // about 2^-46
+{
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+SAKURA_HD inline double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+SAKURA_HD inline double sqrt_step(double x) // about 2^-46, x >= 0
+{
+    if (!(x > 0.0)) return 0.0;
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return x * y;
+}
+
 struct PairFlow {
     double fm1, gmt, fdot, gdm1; // f-1, g-tau, fdot, gdot-1
     int iters;
@@ -79,39 +111,37 @@ struct PairFlow {
     bool safeguarded; // a bisection or bracket-expansion step was needed
 };
 
-// Kepler flow over tau of the relative state (x0, w0) with parameter mu > 0 and
-// r0 = |x0| > 0 (callers substitute a trivial problem otherwise).
+// Kepler flow over tau of the relative state (x0, w0) with parameter mu >= 0
+// and r0^2 = |x0|^2 > 0 (callers substitute a trivial problem otherwise).
 SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1,
                                       double x2, double w0, double w1, double w2,
-                                      const KeplerParams &kp)
+                                      double r0sq, const KeplerParams &kp)
 {
-    const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
-    const double r0 = sqrt(r0sq);
+    const double r0inv = rsqrt_refined(r0sq);
+    const double r0 = r0sq * r0inv;
     const double eta = fma(x0, w0, fma(x1, w1, x2 * w2));
     const double vsq = fma(w0, w0, fma(w1, w1, w2 * w2));
-    const double beta = 2.0 * mu / r0 - vsq;
+    const double beta = fma(2.0 * mu, r0inv, -vsq);
     const double zeta = fma(-beta, r0, mu); // mu - beta r0 = d^2 r / ds^2 at s = 0
 
-    // Bound motion repeats after P = 2 pi mu / beta^{3/2}: a flight longer than
-    // half a period is replaced by its remainder.
     // sqrt(beta) s is the change of eccentric anomaly, so one period spans
     // s = 2 pi / sqrt(beta); with |t| <= P/2 the root lies inside that span.
     double t = tau;
     double s_half = 1e300; // bound on |s| (bound orbits only)
     if (beta > 0.0) {
-        const double sb = sqrt(beta);
-        s_half = 6.3 / sb; // just above 2 pi / sqrt(beta)
-        const double P = 6.283185307179586 * mu / (beta * sb);
-        if (fabs(t) > 0.5 * P) t -= P * rint(t / P);
+        const double ib = rsqrt_refined(beta);
+        s_half = 6.3 * ib; // just above 2 pi / sqrt(beta)
+        const double P = 6.283185307179586 * mu * ib * ib * ib;
+        if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
     }
 
     // Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  Deep
     // in the hyperbolic regime (-beta u^2 > 1) the series overshoots; there
     // t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3) with k = sqrt(-beta)
     // is inverted instead.
-    const double u = t / r0;
-    const double c3s = (3.0 * eta * eta - zeta * r0) / (6.0 * r0sq);
-    double s = u * fma(u * u, c3s, fma(-0.5 * eta / r0, u, 1.0));
+    const double u = t * r0inv;
+    const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
+    double s = u * fma(u * u, c3s, fma(-0.5 * eta * r0inv, u, 1.0));
     if (beta < 0.0 && -beta * u * u > 1.0) {
         const double k = sqrt(-beta);
         const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
@@ -147,16 +177,43 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         if (F < 0.0) lo = s;
         else hi = s;
         const double disc = fma(16.0 * r, r, -20.0 * F * Fpp);
-        const double ds = 5.0 * F / (r + sqrt(fabs(disc)));
-        // Converged when the correction is below tol |s|, or when it sits at
-        // the rounding floor of F (tiny and no longer shrinking).
+        const double ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
         const double ads = fabs(ds), as = fabs(s);
+        // Converged at s: the correction is below tol |s|, or it sits at the
+        // rounding floor of F (tiny and no longer shrinking).
         if (ads <= kp.tol * as || F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * ds_prev)) {
             out.converged = true;
             break;
         }
+        // Converged at s - ds: the error left after the step, estimated from
+        // the derivatives of t(s) -- the Newton term |t2| ds^2 / 2r and the
+        // cubic terms (|t3| / r + (t2 / r)^2) |ds|^3, with t2, t3 the second and
+        // third derivatives -- is below tol |s - ds| (tested without
+        // divisions).  The G-functions are then carried to s - ds by their
+        // Taylor series (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of
+        // being evaluated again.
+        const double sn_l = s - ds;
+        const double asn = fabs(sn_l);
+        const double aFpp = fabs(Fpp);
+        const double Fppp = fma(zeta, G0, -beta * eta * G1);
+        const double ads2 = ads * ads;
+        const double err_r2 = fma(aFpp * ads2, r, ads2 * ads * fma(fabs(Fppp), r, aFpp * aFpp));
+        if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * kp.tol * asn * r * r &&
+            sn_l >= lo && sn_l <= hi) {
+            const double d = -ds, d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
+            const double mbG1 = -beta * G1, mbG0 = -beta * G0;
+            const double nG3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
+            const double nG2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
+            const double nG1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
+            G1 = nG1;
+            G2 = nG2;
+            G3 = nG3;
+            r = fma(eta, G1, fma(zeta, G2, r0));
+            out.converged = true;
+            break;
+        }
         ds_prev = ads;
-        double sn = s - ds;
+        double sn = sn_l;
         // Bisect when the step leaves the bracket or the residual fails to halve
         // (a slow crawl down an exponential); an open bracket is expanded.
         const bool stall = fabs(F) > 0.5 * F_prev && ads > 1e-6 * as;
@@ -168,9 +225,8 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         s = sn;
     }
     out.iters = it;
-    // Coefficients at the converged s (the last correction was below tol |s|).
-    const double rinv = 1.0 / r;
-    const double r0inv = 1.0 / r0;
+    // Lagrange coefficients at the converged s.
+    const double rinv = rcp_refined(r);
     out.fm1 = -mu * G2 * r0inv;
     out.gmt = (t - tau) - mu * G3;
     out.fdot = -mu * G1 * rinv * r0inv;

@@ -9,71 +9,15 @@
 // Per step: k_pairs (eqs. 26, 23 over all unordered pairs) then k_apply
 // (eqs. 27b-d and the next step's 27a); k_import / k_export convert between the
 // caller's [n][3] arrays and the internal layout once per call.
-#include <hip/hip_runtime.h>
+#include "common.hpp"
 
-#include <climits>
-#include <cmath>
-#include <cstdint>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "../../include/sakura.h"
-#include "kepler_device.hpp"
-
-namespace {
-
-constexpr int TILE = 64; // particles per block = lanes per wavefront
-
-enum : unsigned { ST_NONFINITE = 1u, ST_COLLIDE = 2u, ST_NOCONV = 4u, ST_INVAL = 8u };
-
-struct DevCounters {
-    unsigned status; // ST_* bits
-    unsigned iters_max;
-    unsigned long long pair_solves;
-    unsigned long long iters_total;
-    unsigned long long fallbacks;
-    long long failed_step;
-    unsigned hist[32];
-};
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-__device__ inline unsigned wave_sum(unsigned x)
+__global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
 {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-__device__ inline unsigned wave_max(unsigned x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = max(x, (unsigned)__shfl_xor(x, o, 64));
-    return x;
-}
-__device__ inline unsigned wave_or(unsigned x)
-{
-    for (int o = 32; o > 0; o >>= 1) x |= (unsigned)__shfl_xor(x, o, 64);
-    return x;
-}
-__device__ inline double wave_sum_d(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-__device__ inline void record_error(DevCounters *c, unsigned bits, long long step)
-{
-    atomicOr(&c->status, bits);
-    atomicMin(&c->failed_step, step);
-}
-
-// ---------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------
-__global__ void k_clear(DevCounters *c)
-{
-    const int t = threadIdx.x;
+    const int t = threadIdx.x; // NSLOT threads
+    slots[t].pair_solves = 0;
+    slots[t].iters_total = 0;
+    slots[t].fallbacks = 0;
+    slots[t].iters_max = 0;
     if (t == 0) {
         c->status = 0;
         c->iters_max = 0;
@@ -81,9 +25,41 @@ __global__ void k_clear(DevCounters *c)
         c->iters_total = 0;
         c->fallbacks = 0;
         c->failed_step = LLONG_MAX;
+        c->work_next = 0;
     }
     if (t < 32) c->hist[t] = 0;
 }
+
+// Sum of the counter slots (fixed order, one workgroup of NSLOT threads).
+__global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
+{
+    __shared__ unsigned long long a[NSLOT], b[NSLOT], f[NSLOT];
+    __shared__ unsigned mx[NSLOT];
+    const int t = threadIdx.x;
+    a[t] = slots[t].pair_solves;
+    b[t] = slots[t].iters_total;
+    f[t] = slots[t].fallbacks;
+    mx[t] = slots[t].iters_max;
+    __syncthreads();
+    for (int w = NSLOT / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            a[t] += a[t + w];
+            b[t] += b[t + w];
+            f[t] += f[t + w];
+            mx[t] = max(mx[t], mx[t + w]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        c->pair_solves = a[0];
+        c->iters_total = b[0];
+        c->fallbacks = f[0];
+        c->iters_max = mx[0];
+    }
+}
+
+namespace {
+using namespace sk;
 
 // Caller layout -> SoA, with the half drift of eq. (27a) into the row r_half.
 __global__ void k_import(int n, int np, const double *__restrict__ m,
@@ -112,20 +88,31 @@ __global__ void k_import(int n, int np, const double *__restrict__ m,
     }
 }
 
+// Value held by lane (l + 1) mod 64, for every lane l: a whole-wave rotate
+// (DPP wave_rol:1) applied to both halves of a double.
+__device__ inline double from_next_lane(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x134, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
 //
-// Lane l holds particle i = 64 I + l; block J sits in LDS.  In sub-step s lane
-// l takes the pair (i, 64 J + ((l + s) mod 64)), so within a sub-step every
-// lane touches a different j and the j-side sums (Newton's third law) are
-// updated in LDS without conflicts or atomics.  The diagonal tile runs
+// Lane l holds particle i = 64 I + l; block J sits in LDS (read only).  In
+// sub-step s lane l takes the pair (i, 64 J + ((l + s) mod 64)), so within a
+// sub-step every lane touches a different j.  The j-side sums (Newton's third
+// law) live in registers and follow their j: after each sub-step every lane
+// takes the sums of lane l + 1, which is the j it meets next.  No atomics, no
+// LDS writes and no barrier inside the loop.  The diagonal tile runs
 // s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
 // Partial sums go to part[I][J] (i side) and part[J][I] (j side).
 template <bool HIST>
 __global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
                                                 double *__restrict__ part,
-                                                DevCounters *cnt, kep::KeplerParams kp,
-                                                long long step)
+                                                DevCounters *cnt, SlotStats *slots,
+                                                kep::KeplerParams kp, long long step)
 {
     if (cnt->status) return; // an earlier failure: the call will report it
     const int t = blockIdx.x;
@@ -147,11 +134,13 @@ __global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double ta
     const double *V = S + 4 * (size_t)np;
     const double *XH = S + 7 * (size_t)np;
 
-    __shared__ double sj[7][TILE]; // x y z vx vy vz m of block J
-    __shared__ double sa[6][TILE]; // j-side sums
+    __shared__ double sj[7][TILE]; // x y z vx vy vz m of block J; later the j-side sums
+    __shared__ double si[7][TILE]; // the same for block I (each lane reads its own slot)
+    __shared__ double sacc[6][TILE]; // i-side sums, one slot per lane
     __shared__ unsigned shist[HIST ? 32 : 1];
 
     const int jg = J * TILE + lane;
+    const int ig = I * TILE + lane;
     sj[0][lane] = XH[jg];
     sj[1][lane] = XH[np + jg];
     sj[2][lane] = XH[2 * (size_t)np + jg];
@@ -159,44 +148,56 @@ __global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double ta
     sj[4][lane] = V[np + jg];
     sj[5][lane] = V[2 * (size_t)np + jg];
     sj[6][lane] = M[jg];
-    for (int c = 0; c < 6; ++c) sa[c][lane] = 0.0;
+    si[0][lane] = XH[ig];
+    si[1][lane] = XH[np + ig];
+    si[2][lane] = XH[2 * (size_t)np + ig];
+    si[3][lane] = V[ig];
+    si[4][lane] = V[np + ig];
+    si[5][lane] = V[2 * (size_t)np + ig];
+    si[6][lane] = M[ig];
+    for (int c = 0; c < 6; ++c) sacc[c][lane] = 0.0;
     if (HIST && lane < 32) shist[lane] = 0;
 
-    const int ig = I * TILE + lane;
-    const double xi = XH[ig], yi = XH[np + ig], zi = XH[2 * (size_t)np + ig];
-    const double ui = V[ig], vi = V[np + ig], wi = V[2 * (size_t)np + ig];
-    const double mi = M[ig];
     const bool valid_i = ig < n;
     const double h = 0.5 * tau;
+    const int nj = n - J * TILE; // valid j slots in this block
 
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    unsigned it_sum = 0, it_max = 0, n_solve = 0, n_fb = 0, flags = 0;
+    double jac[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // sums of slot (lane + s) mod 64
+    unsigned it_sum = 0, it_max = 0;          // per lane
+    unsigned long long n_solve = 0, n_fb = 0; // per wave (ballot counts)
+    bool any_noconv = false, any_collide = false;
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
     for (int s = s0; s < s1; ++s) {
         const int q = (lane + s) & (TILE - 1);
-        const double mj = sj[6][q];
+        // Particle data are read from LDS at every use (compiler-only fence:
+        // keeps them out of registers across the Kepler solve).
+        asm volatile("" ::: "memory");
+        const double mi = si[6][lane], mj = sj[6][q];
         const double msum = mi + mj;
-        const bool act = valid_i && (J * TILE + q < n) && (msum > 0.0) &&
+        const bool act = valid_i && (q < nj) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         // relative state and the pair back-drift of eq. (17) by tau/2
-        const double W0 = ui - sj[3][q], W1 = vi - sj[4][q], W2 = wi - sj[5][q];
-        double x0 = fma(-h, W0, xi - sj[0][q]);
-        double x1 = fma(-h, W1, yi - sj[1][q]);
-        double x2 = fma(-h, W2, zi - sj[2][q]);
+        double w0 = si[3][lane] - sj[3][q], w1 = si[4][lane] - sj[4][q], w2 = si[5][lane] - sj[5][q];
+        double x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
+        double x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
+        double x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
         const bool live = act && !collide;
-        // lanes without a pair solve a trivial problem (tau = 0, mu = 0)
-        const double tt = live ? tau : 0.0;
-        const double mu = live ? G * msum : 0.0;
-        x0 = live ? x0 : 1.0;
-        x1 = live ? x1 : 0.0;
-        x2 = live ? x2 : 0.0;
-        const double w0 = live ? W0 : 0.0, w1 = live ? W1 : 0.0, w2 = live ? W2 : 0.0;
-
-        const kep::PairFlow f = kep::kepler_flow(tt, mu, x0, x1, x2, w0, w1, w2, kp);
+        // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
+        const kep::PairFlow f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0,
+                                                 x0, x1, x2, w0, w1, w2,
+                                                 live ? r0sq : 1.0, kp);
+        // the same relative state again, from LDS (bitwise equal to the above)
+        asm volatile("" ::: "memory");
+        w0 = si[3][lane] - sj[3][q];
+        w1 = si[4][lane] - sj[4][q];
+        w2 = si[5][lane] - sj[5][q];
+        x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
+        x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
+        x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
 
         // increments of eq. (26) minus the starting relative state
         const double a = fma(-h, f.fdot, f.fm1);
@@ -205,47 +206,46 @@ __global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double ta
                              fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
                              fma(f.fdot, x2, f.gdm1 * w2)};
         // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j)
-        const double inv = live ? 1.0 / msum : 0.0;
+        const double inv = live ? kep::rcp_refined(msum) : 0.0;
         const double wgt_i = mj * inv, wgt_j = mi * inv;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            acc[c] = fma(wgt_i, d[c], acc[c]);
-            sa[c][q] = fma(-wgt_j, d[c], sa[c][q]);
+            sacc[c][lane] = fma(wgt_i, d[c], sacc[c][lane]);
+            jac[c] = from_next_lane(fma(-wgt_j, d[c], jac[c]));
         }
-        if (live) {
-            ++n_solve;
-            it_sum += f.iters;
-            it_max = max(it_max, (unsigned)f.iters);
-            n_fb += f.safeguarded ? 1u : 0u;
-            if (!f.converged) flags |= ST_NOCONV;
-            if (HIST) atomicAdd(&shist[min(f.iters, 31)], 1u);
-        }
-        if (collide) flags |= ST_COLLIDE;
-        __syncthreads(); // j-side sums of this sub-step visible to the next
+        it_sum += live ? f.iters : 0;
+        it_max = max(it_max, live ? (unsigned)f.iters : 0u);
+        n_solve += __popcll(__ballot(live));
+        n_fb += __popcll(__ballot(live && f.safeguarded));
+        any_noconv = any_noconv || __ballot(live && !f.converged) != 0;
+        any_collide = any_collide || __ballot(collide) != 0;
+        if (HIST && live) atomicAdd(&shist[min(f.iters, 31)], 1u);
     }
 
+    // After the last rotation lane l holds the sums of slot (l + s1) mod 64;
+    // put them in place through LDS.
+    __syncthreads();
+    const int slot = (lane + s1) & (TILE - 1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sj[c][slot] = jac[c];
+    __syncthreads();
     const size_t cs = TILE; // component stride inside a partial
     double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
     if (diag) {
-        for (int c = 0; c < 6; ++c) pij[c * cs] = acc[c] + sa[c][lane];
+        for (int c = 0; c < 6; ++c) pij[c * cs] = sacc[c][lane] + sj[c][lane];
     } else {
         double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
         for (int c = 0; c < 6; ++c) {
-            pij[c * cs] = acc[c];
-            pji[c * cs] = sa[c][lane];
+            pij[c * cs] = sacc[c][lane];
+            pji[c * cs] = sj[c][lane];
         }
     }
 
-    n_solve = wave_sum(n_solve);
     it_sum = wave_sum(it_sum);
-    n_fb = wave_sum(n_fb);
     it_max = wave_max(it_max);
-    flags = wave_or(flags);
+    const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
     if (lane == 0) {
-        atomicAdd(&cnt->pair_solves, (unsigned long long)n_solve);
-        atomicAdd(&cnt->iters_total, (unsigned long long)it_sum);
-        atomicAdd(&cnt->fallbacks, (unsigned long long)n_fb);
-        atomicMax(&cnt->iters_max, it_max);
+        slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
         if (flags) record_error(cnt, flags, step);
     }
     if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
@@ -408,60 +408,6 @@ __global__ void k_energy_final(int ntiles, int nblk, double G, const double *__r
     }
 }
 
-} // namespace
-
-// ---------------------------------------------------------------------------
-// host side
-// ---------------------------------------------------------------------------
-struct sakura {
-    int device = 0;
-    sakura_opts opts{};
-    std::string err;
-    double *state = nullptr; // [10][np]
-    int64_t cap_np = 0;
-    double *part = nullptr; // [nb][nb][6][64]
-    int64_t cap_part = 0;
-    double *scratch_e = nullptr; // energy partials
-    int64_t cap_e = 0;
-    DevCounters *cnt = nullptr;
-    DevCounters *host_cnt = nullptr; // pinned
-    double *host_out = nullptr;      // pinned, 12 doubles
-    std::vector<hipEvent_t> events;
-};
-
-namespace {
-
-int fail(sakura_t *h, int code, const std::string &msg)
-{
-    if (h) h->err = msg;
-    return code;
-}
-
-#define SAKURA_HIP(h, call)                                                                  \
-    do {                                                                                     \
-        hipError_t e_ = (call);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail((h), SAKURA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-int grow(sakura_t *h, double **buf, int64_t *cap, int64_t need)
-{
-    if (*cap >= need) return SAKURA_OK;
-    if (*buf) {
-        SAKURA_HIP(h, hipFree(*buf));
-        *buf = nullptr;
-        *cap = 0;
-    }
-    if (hipMalloc((void **)buf, (size_t)need * sizeof(double)) != hipSuccess) {
-        *buf = nullptr;
-        return fail(h, SAKURA_ENOMEM, "device allocation of " +
-                                          std::to_string((size_t)need * sizeof(double)) +
-                                          " bytes failed");
-    }
-    *cap = need;
-    return SAKURA_OK;
-}
-
 int need_events(sakura_t *h, size_t count)
 {
     while (h->events.size() < count) {
@@ -470,26 +416,6 @@ int need_events(sakura_t *h, size_t count)
         h->events.push_back(e);
     }
     return SAKURA_OK;
-}
-
-int status_code(unsigned st)
-{
-    if (st & ST_INVAL) return SAKURA_EINVAL;
-    if (st & ST_NONFINITE) return SAKURA_ENONFINITE;
-    if (st & ST_COLLIDE) return SAKURA_ECOLLIDE;
-    if (st & ST_NOCONV) return SAKURA_ENOCONV;
-    return SAKURA_OK;
-}
-
-const char *status_text(int code)
-{
-    switch (code) {
-    case SAKURA_EINVAL: return "negative mass";
-    case SAKURA_ENONFINITE: return "non-finite position, velocity or mass";
-    case SAKURA_ECOLLIDE: return "two particles at zero separation (no softening)";
-    case SAKURA_ENOCONV: return "a Kepler solve did not converge";
-    default: return "";
-    }
 }
 
 } // namespace
@@ -513,8 +439,9 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
         return SAKURA_ENOMODEL;
     }
     if (hipSetDevice(device) != hipSuccess ||
-        hipMalloc((void **)&h->cnt, sizeof(DevCounters)) != hipSuccess ||
-        hipHostMalloc((void **)&h->host_cnt, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&h->cnt, sizeof(sk::DevCounters)) != hipSuccess ||
+        hipMalloc((void **)&h->slots, sk::NSLOT * sizeof(sk::SlotStats)) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_cnt, sizeof(sk::DevCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&h->host_out, 12 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         sakura_destroy(h);
         return SAKURA_EHIP;
@@ -532,8 +459,16 @@ void sakura_destroy(sakura_t *h)
     if (h->part) (void)hipFree(h->part);
     if (h->scratch_e) (void)hipFree(h->scratch_e);
     if (h->cnt) (void)hipFree(h->cnt);
+    if (h->slots) (void)hipFree(h->slots);
     if (h->host_cnt) (void)hipHostFree(h->host_cnt);
     if (h->host_out) (void)hipHostFree(h->host_out);
+    if (h->batch_state) (void)hipFree(h->batch_state);
+    if (h->batch_work) (void)hipFree(h->batch_work);
+    if (h->batch_offsets) (void)hipFree(h->batch_offsets);
+    if (h->tune_rv) (void)hipFree(h->tune_rv);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     delete h;
 }
 
@@ -548,20 +483,20 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
         std::memset(stats, 0, sizeof(*stats));
         stats->failed_step = -1;
     }
-    if (n < 1 || !m || !r || !v) return fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
-    if (n > ((int64_t)1 << 21)) return fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
+    if (n < 1 || !m || !r || !v) return sk::fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
+    if (n > ((int64_t)1 << 21)) return sk::fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
     if (!std::isfinite(dt) || !std::isfinite(G) || G < 0.0)
-        return fail(h, SAKURA_EINVAL, "dt and G must be finite and G >= 0");
-    if (nsteps < 0) return fail(h, SAKURA_EINVAL, "nsteps < 0");
+        return sk::fail(h, SAKURA_EINVAL, "dt and G must be finite and G >= 0");
+    if (nsteps < 0) return sk::fail(h, SAKURA_EINVAL, "nsteps < 0");
     if (nsteps == 0) return SAKURA_OK;
 
     SAKURA_HIP(h, hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
-    const int nb = (int)((n + TILE - 1) / TILE);
-    const int np = nb * TILE;
+    const int nb = (int)((n + sk::TILE - 1) / sk::TILE);
+    const int np = nb * sk::TILE;
     int rc;
-    if ((rc = grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
-    if ((rc = grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * TILE))) return rc;
+    if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
+    if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE))) return rc;
     const bool timing = stats != nullptr;
     if (timing && (rc = need_events(h, 2 + 2 * (size_t)nsteps))) return rc;
 
@@ -570,26 +505,27 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
-    k_clear<<<1, 64, 0, st>>>(h->cnt);
+    sk::k_clear<<<1, sk::NSLOT, 0, st>>>(h->cnt, h->slots);
     k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, half, h->state, h->cnt);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * s], st));
         if (h->opts.histogram)
-            k_pairs<true><<<ntiles, TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
-                                                   h->cnt, kp, s);
+            k_pairs<true><<<ntiles, sk::TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
+                                                   h->cnt, h->slots, kp, s);
         else
-            k_pairs<false><<<ntiles, TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
-                                                    h->cnt, kp, s);
+            k_pairs<false><<<ntiles, sk::TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
+                                                    h->cnt, h->slots, kp, s);
         if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * s], st));
-        k_apply<<<nb, 6 * TILE, 0, st>>>((int)n, nb, np, half, h->state, h->part, h->cnt, s);
+        k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, half, h->state, h->part, h->cnt, s);
     }
     k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, h->state, r, v, h->cnt);
+    sk::k_fold_stats<<<1, sk::NSLOT, 0, st>>>(h->slots, h->cnt);
     SAKURA_HIP(h, hipGetLastError());
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[1], st));
-    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, h->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, st));
+    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, h->cnt, sizeof(sk::DevCounters), hipMemcpyDeviceToHost, st));
     SAKURA_HIP(h, hipStreamSynchronize(st));
 
-    const DevCounters &c = *h->host_cnt;
+    const sk::DevCounters &c = *h->host_cnt;
     if (stats) {
         stats->pair_solves = c.pair_solves;
         stats->iters_total = c.iters_total;
@@ -608,8 +544,8 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
         SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
         stats->call_ms = ms;
     }
-    const int code = status_code(c.status);
-    if (code) return fail(h, code, std::string(status_text(code)) + " at step " +
+    const int code = sk::status_code(c.status);
+    if (code) return sk::fail(h, code, std::string(sk::status_text(code)) + " at step " +
                                        std::to_string(c.failed_step));
     return SAKURA_OK;
 }
@@ -625,18 +561,18 @@ int sakura_energy(sakura_t *h, int64_t n, const double *m, const double *r, cons
 {
     if (!h) return SAKURA_EINVAL;
     h->err.clear();
-    if (n < 1 || !m || !r || !v || !out) return fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
-    if (n > ((int64_t)1 << 21)) return fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
-    if (!std::isfinite(G)) return fail(h, SAKURA_EINVAL, "G must be finite");
+    if (n < 1 || !m || !r || !v || !out) return sk::fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
+    if (n > ((int64_t)1 << 21)) return sk::fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
+    if (!std::isfinite(G)) return sk::fail(h, SAKURA_EINVAL, "G must be finite");
     SAKURA_HIP(h, hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
-    const int nb = (int)((n + TILE - 1) / TILE);
+    const int nb = (int)((n + sk::TILE - 1) / sk::TILE);
     const int ntiles = nb * (nb + 1) / 2;
     int rc;
-    if ((rc = grow(h, &h->scratch_e, &h->cap_e, (int64_t)ntiles + 11 * (int64_t)nb + 12))) return rc;
+    if ((rc = sk::grow(h, &h->scratch_e, &h->cap_e, (int64_t)ntiles + 11 * (int64_t)nb + 12))) return rc;
     double *tile_u = h->scratch_e, *blk = tile_u + ntiles, *dout = blk + 11 * (size_t)nb;
-    k_energy_pairs<<<ntiles, TILE, 0, st>>>((int)n, nb, m, r, tile_u);
-    k_energy_bodies<<<nb, TILE, 0, st>>>((int)n, m, r, v, blk);
+    k_energy_pairs<<<ntiles, sk::TILE, 0, st>>>((int)n, nb, m, r, tile_u);
+    k_energy_bodies<<<nb, sk::TILE, 0, st>>>((int)n, m, r, v, blk);
     k_energy_final<<<1, 64, 0, st>>>(ntiles, nb, G, tile_u, blk, dout);
     SAKURA_HIP(h, hipGetLastError());
     SAKURA_HIP(h, hipMemcpyAsync(h->host_out, dout, 12 * sizeof(double), hipMemcpyDeviceToHost, st));

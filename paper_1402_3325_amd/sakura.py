@@ -70,6 +70,18 @@ def load_library():
     L.sakura_energy.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), P]
     L.sakura_energy.restype = ctypes.c_int
+    L.sakura_batch_evolve.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P, P,
+                                      P, ctypes.c_int64, ctypes.c_double, P,
+                                      ctypes.POINTER(Stats)]
+    L.sakura_batch_evolve.restype = ctypes.c_int
+    L.sakura_batch_set_policy.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.sakura_batch_set_policy.restype = ctypes.c_int
+    L.sakura_batch_set_group.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    L.sakura_batch_set_group.restype = ctypes.c_int
+    L.sakura_autotune_batch.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P, P,
+                                        P, ctypes.c_int64, ctypes.c_double, P,
+                                        ctypes.POINTER(ctypes.c_double)]
+    L.sakura_autotune_batch.restype = ctypes.c_int
     L.sakura_last_error.argtypes = [P]
     L.sakura_last_error.restype = ctypes.c_char_p
     return L
@@ -153,6 +165,52 @@ class Sakura:
         if rc != OK:
             self._raise(rc)
         return st.to_dict() if stats else None
+
+    def _batch_args(self, offsets, m, r, v, dt):
+        import numpy as np
+        import torch
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        nsys = off.shape[0] - 1
+        n = _check_state(m, r, v)
+        if nsys < 1 or off[0] != 0 or off[-1] != n:
+            raise ValueError("offsets must start at 0 and end at len(m)")
+        if not (isinstance(dt, torch.Tensor) and dt.dtype == torch.float64 and dt.is_cuda
+                and dt.is_contiguous() and tuple(dt.shape) == (nsys,)):
+            raise TypeError("dt must be a contiguous float64 CUDA tensor of shape [nsys]")
+        return off, nsys
+
+    def batch_evolve(self, offsets, m, r, v, dt, nsteps: int, G: float = 1.0, stats: bool = False):
+        """nsteps steps of every system of a CSR ensemble (offsets: host int64
+        [nsys+1]; dt: per-system steps, CUDA float64 [nsys])."""
+        off, nsys = self._batch_args(offsets, m, r, v, dt)
+        st = Stats()
+        rc = self._lib.sakura_batch_evolve(
+            self._h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+            ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(dt.data_ptr()), int(nsteps),
+            float(G), self._stream(m), ctypes.byref(st) if stats else None)
+        if rc != OK:
+            self._raise(rc)
+        return st.to_dict() if stats else None
+
+    def batch_set_policy(self, policy: int = 0, waves_per_cu: int = 8, use_graph: bool = True):
+        rc = self._lib.sakura_batch_set_policy(self._h, policy, waves_per_cu, int(bool(use_graph)))
+        if rc != OK:
+            self._raise(rc)
+
+    def autotune_batch(self, offsets, m, r, v, dt, probe_steps: int = 8, G: float = 1.0):
+        """Pick the fastest packing policy and grid size for this ensemble
+        (r, v are not modified).  Returns the best probe time in ms."""
+        off, nsys = self._batch_args(offsets, m, r, v, dt)
+        best = ctypes.c_double(0.0)
+        rc = self._lib.sakura_autotune_batch(
+            self._h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+            ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(dt.data_ptr()), int(probe_steps),
+            float(G), self._stream(m), ctypes.byref(best))
+        if rc != OK:
+            self._raise(rc)
+        return best.value
 
     def energy(self, m, r, v, G: float = 1.0):
         """{E, K, U, P, L, Rcm} of eqs. (1-3), computed on the GPU."""

@@ -1,0 +1,155 @@
+"""Batched ensembles (sakura_batch_evolve) vs the oracle, system by system.
+
+Same per-step error metric and 1e-12 tolerance as the single-system tests;
+r_rms and v_rms are taken per system.
+"""
+import numpy as np
+import pytest
+
+from paper_1402_3325_amd import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def lib(torch):
+    from paper_1402_3325_amd.sakura import Sakura
+    h = Sakura(0)
+    yield h
+    h.close()
+
+
+def small_ensemble(sizes, seed=5):
+    """Planetary systems of the given sizes (a size-1 system is a lone star)."""
+    ms, rs, vs, ts = [], [], [], []
+    rng = np.random.default_rng(seed)
+    for n in sizes:
+        if n == 1:
+            m, r, v, tau = np.array([1.0]), rng.normal(size=(1, 3)), rng.normal(size=(1, 3)), 0.1
+        else:
+            m, r, v, tau = workloads.planetary(n - 1, rng=rng)
+        ms.append(m)
+        rs.append(r)
+        vs.append(v)
+        ts.append(tau)
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off, np.concatenate(ms), np.concatenate(rs), np.concatenate(vs), np.array(ts)
+
+
+def _dev(torch, *a):
+    return [torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda") for x in a]
+
+
+def sys_error(rg, vg, ro, vo, rin, vin):
+    r_rms = np.sqrt(np.mean(np.sum(rin ** 2, 1)))
+    v_rms = np.sqrt(np.mean(np.sum(vin ** 2, 1)))
+    er = np.max(np.linalg.norm(rg - ro, axis=1) / np.maximum(np.linalg.norm(ro, axis=1), r_rms))
+    ev = np.max(np.linalg.norm(vg - vo, axis=1) / np.maximum(np.linalg.norm(vo, axis=1), v_rms))
+    return er, ev
+
+
+SIZES = [1, 2, 3, 4, 5, 7, 8, 16, 17, 21, 31, 32, 33, 47, 63, 64, 64, 3, 3, 3, 3, 3, 12, 12, 12]
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_batch_matches_oracle_every_step(torch, lib, oracle, policy):
+    lib.batch_set_policy(policy, 8, True)
+    off, m, r, v, tau = small_ensemble(SIZES)
+    for step in range(4):
+        mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+        lib.batch_evolve(off, mt, rt, vt, dtt, 1)
+        rg, vg = rt.cpu().numpy(), vt.cpu().numpy()
+        rn, vn = r.copy(), v.copy()
+        for s in range(len(SIZES)):
+            a, b = off[s], off[s + 1]
+            ro, vo = oracle.step(m[a:b], r[a:b], v[a:b], tau[s])
+            er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
+            assert er <= TOL and ev <= TOL, (policy, step, s, SIZES[s], er, ev)
+            rn[a:b], vn[a:b] = ro, vo
+        r, v = rn, vn
+    lib.batch_set_policy(0, 8, True)
+
+
+def test_batch_equals_single_system_path(torch, lib):
+    off, m, r, v, tau = small_ensemble([64, 40, 9, 2], seed=9)
+    mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+    st = lib.batch_evolve(off, mt, rt, vt, dtt, 10, stats=True)
+    assert st["pair_solves"] == 10 * sum(n * (n - 1) // 2 for n in (64, 40, 9, 2))
+    rb, vb = rt.cpu().numpy(), vt.cpu().numpy()
+    for s in range(4):
+        a, b = off[s], off[s + 1]
+        ms, rs, vs = _dev(torch, m[a:b], r[a:b], v[a:b])
+        lib.evolve(ms, rs, vs, float(tau[s]), 10)
+        er, ev = sys_error(rb[a:b], vb[a:b], rs.cpu().numpy(), vs.cpu().numpy(), r[a:b], v[a:b])
+        assert er <= 1e-11 and ev <= 1e-11, (s, er, ev)
+
+
+def test_graph_replays_match_eager(torch, lib):
+    """The captured graph is replayed several times with eager work and
+    synchronisations in between; every replay equals the eager launch."""
+    off, m, r, v, tau = small_ensemble(SIZES, seed=21)
+    lib.batch_set_policy(0, 8, False)
+    mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+    lib.batch_evolve(off, mt, rt, vt, dtt, 6)
+    r_eager, v_eager = rt.cpu().numpy(), vt.cpu().numpy()
+    lib.batch_set_policy(0, 8, True)
+    r0, v0 = _dev(torch, r, v)
+    for rep in range(4):
+        rt.copy_(r0)
+        vt.copy_(v0)
+        torch.cuda.synchronize()
+        _ = (rt * 2.0).sum().item()  # unrelated eager work between replays
+        lib.batch_evolve(off, mt, rt, vt, dtt, 6)
+        assert np.array_equal(rt.cpu().numpy(), r_eager), rep
+        assert np.array_equal(vt.cpu().numpy(), v_eager), rep
+
+
+def test_batch_errors_update_nothing(torch, lib):
+    from paper_1402_3325_amd.sakura import SakuraError, ENONFINITE, EINVAL
+    off, m, r, v, tau = small_ensemble([5, 6, 7], seed=3)
+    rb = r.copy()
+    rb[8, 0] = np.nan
+    mt, rt, vt, dtt = _dev(torch, m, rb, v, tau)
+    with pytest.raises(SakuraError) as e:
+        lib.batch_evolve(off, mt, rt, vt, dtt, 3)
+    assert e.value.code == ENONFINITE
+    assert np.array_equal(rt.cpu().numpy(), rb, equal_nan=True)
+    assert np.array_equal(vt.cpu().numpy(), v)
+    mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+    with pytest.raises(SakuraError) as e:
+        lib.batch_evolve(np.array([0, 5, 5, 18]), mt, rt, vt, dtt, 1)
+    assert e.value.code == EINVAL
+    # a system of 65 particles is beyond the batched path
+    mt, rt, vt = _dev(torch, np.ones(65), np.random.default_rng(0).normal(size=(65, 3)),
+                      np.zeros((65, 3)))
+    with pytest.raises(SakuraError) as e:
+        lib.batch_evolve(np.array([0, 65]), mt, rt, vt, _dev(torch, np.array([0.1]))[0], 1)
+    assert e.value.code == EINVAL
+
+
+def test_ensemble_4096_sampled_systems(torch, lib, oracle):
+    """The full ensemble (4096 planetary systems, n in [3, 64]): one step of
+    every system in the benchmark's configuration, sampled systems compared
+    with the oracle."""
+    off, m, r, v, tau = workloads.ensemble()
+    mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+    st = lib.batch_evolve(off, mt, rt, vt, dtt, 1, stats=True)
+    sizes = np.diff(off)
+    assert st["pair_solves"] == int(np.sum(sizes * (sizes - 1) // 2))
+    rg, vg = rt.cpu().numpy(), vt.cpu().numpy()
+    rng = np.random.default_rng(8)
+    for s in rng.choice(len(sizes), 64, replace=False):
+        a, b = off[s], off[s + 1]
+        ro, vo = oracle.step(m[a:b], r[a:b], v[a:b], tau[s])
+        er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
+        assert er <= TOL and ev <= TOL, (s, sizes[s], er, ev)
