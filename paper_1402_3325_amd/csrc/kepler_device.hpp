@@ -104,12 +104,113 @@ SAKURA_HD inline double sqrt_step(double x) // about 2^-46, x >= 0
     return x * y;
 }
 
+// The same functions for |z| <= 2^-10 only: four terms each leave a truncation
+// below 1e-18 relative.
+SAKURA_HD inline void stumpff23_small(double z, double &c2, double &c3)
+{
+    c2 = fma(fma(fma(-z, 1.0 / 40320.0, 1.0 / 720.0), -z, 1.0 / 24.0), -z, 0.5);
+    c3 = fma(fma(fma(-z, 1.0 / 362880.0, 1.0 / 5040.0), -z, 1.0 / 120.0), -z, 1.0 / 6.0);
+}
+
+#ifndef SAKURA_WAVE_ALL
+#define SAKURA_WAVE_ALL(pred) __all(pred) // every active lane of the wavefront
+#endif
+
 struct PairFlow {
     double fm1, gmt, fdot, gdm1; // f-1, g-tau, fdot, gdot-1
     int iters;
     bool converged;
     bool safeguarded; // a bisection or bracket-expansion step was needed
 };
+
+// State of the root search on t(s) = tau.
+struct KepIter {
+    double s, lo, hi;       // iterate and bracket
+    double ds_prev, F_prev; // for the stall tests
+    double G1, G2, G3, r;   // G-functions and radius at the accepted root
+    bool safeguarded;
+};
+
+// One evaluation of t(s) - tau at st.s and its Laguerre step (order 5).
+// Returns 1 when st.s is the root (G-functions and r left at st.s), 2 when
+// st.s - ds is (G-functions carried there by their Taylor series), 0 when the
+// search goes on from the new st.s.
+template <bool SMALL_Z>
+SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double zeta,
+                                    double r0, double t, double tol)
+{
+    const double s = st.s;
+    const double z = beta * s * s;
+    double c2, c3;
+    if (SMALL_Z) stumpff23_small(z, c2, c3);
+    else stumpff23(z, c2, c3);
+    const double s2 = s * s;
+    const double G1 = s * fma(-z, c3, 1.0);
+    const double G2 = s2 * c2;
+    const double G3 = s2 * s * c3;
+    const double G0 = fma(-z, c2, 1.0);
+    const double F = fma(r0, s, fma(eta, G2, fma(zeta, G3, -t)));
+    const double r = fma(eta, G1, fma(zeta, G2, r0));
+    const double Fpp = fma(eta, G0, zeta * G1);
+    if (F < 0.0) st.lo = s;
+    else st.hi = s;
+    const double disc = fma(16.0 * r, r, -20.0 * F * Fpp);
+    const double ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
+    const double ads = fabs(ds), as = fabs(s);
+    // Converged at s: the correction is below tol |s|, or it sits at the
+    // rounding floor of F (tiny and no longer shrinking).
+    if (ads <= tol * as || F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * st.ds_prev)) {
+        st.G1 = G1;
+        st.G2 = G2;
+        st.G3 = G3;
+        st.r = r;
+        return 1;
+    }
+    // Converged at s - ds: the error left after the step, estimated from the
+    // derivatives of t(s) -- the Newton term |t2| ds^2 / 2r and the cubic
+    // terms (|t3| / r + (t2 / r)^2) |ds|^3, with t2, t3 the second and third
+    // derivatives -- is below tol |s - ds| (tested without divisions).  The
+    // G-functions are then carried to s - ds by their Taylor series
+    // (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of being evaluated again.
+    const double sn = s - ds;
+    const double asn = fabs(sn);
+    const double aFpp = fabs(Fpp);
+    const double Fppp = fma(zeta, G0, -beta * eta * G1);
+    const double ads2 = ads * ads;
+    const double err_r2 = fma(aFpp * ads2, r, ads2 * ads * fma(fabs(Fppp), r, aFpp * aFpp));
+    if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * r * r && sn >= st.lo &&
+        sn <= st.hi) {
+        const double d = -ds, d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
+        const double mbG1 = -beta * G1, mbG0 = -beta * G0;
+        st.G3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
+        st.G2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
+        st.G1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
+        st.r = fma(eta, st.G1, fma(zeta, st.G2, r0));
+        st.s = sn;
+        return 2;
+    }
+    // Safeguard when the step leaves the bracket, or when the search crawls:
+    // the residual fails to halve, or a large step fails to halve (linear
+    // progress down an exponential).  A crawl inside a bracket much wider
+    // than the step doubles the step; otherwise bisect, and an open bracket
+    // is expanded.
+    const bool stall = (fabs(F) > 0.5 * st.F_prev && ads > 1e-6 * as) ||
+                       (ads > 0.5 * st.ds_prev && ads > 1e-3 * as);
+    double next = sn;
+    const bool inside = next >= st.lo && next <= st.hi;
+    if (!inside || stall) {
+        const double ext = s - 2.0 * ds;
+        if (inside && ext > st.lo && ext < st.hi && 8.0 * ads < st.hi - st.lo)
+            next = ext;
+        else
+            next = (st.hi - st.lo < 1e299) ? 0.5 * (st.lo + st.hi) : 2.0 * s;
+        st.safeguarded = true;
+    }
+    st.ds_prev = ads;
+    st.F_prev = fabs(F);
+    st.s = next;
+    return 0;
+}
 
 // Kepler flow over tau of the relative state (x0, w0) with parameter mu >= 0
 // and r0^2 = |x0|^2 > 0 (callers substitute a trivial problem otherwise).
@@ -135,95 +236,53 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
     }
 
-    // Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  Deep
-    // in the hyperbolic regime (-beta u^2 > 1) the series overshoots; there
-    // t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3) with k = sqrt(-beta)
-    // is inverted instead.
+    // Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  When
+    // its corrections dominate the series is no guide: start from the free
+    // drift u instead, or, deep in the hyperbolic regime (-beta u^2 > 1), from
+    // the inversion of t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3),
+    // k = sqrt(-beta).
     const double u = t * r0inv;
     const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
-    double s = u * fma(u * u, c3s, fma(-0.5 * eta * r0inv, u, 1.0));
-    if (beta < 0.0 && -beta * u * u > 1.0) {
-        const double k = sqrt(-beta);
-        const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
-        s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
+    const double corr1 = -0.5 * eta * r0inv * u, corr2 = c3s * u * u;
+    double s = u * (1.0 + corr1 + corr2);
+    if (fabs(corr1) + fabs(corr2) > 0.5) {
+        s = u;
+        if (beta < 0.0 && -beta * u * u > 1.0) {
+            const double k = sqrt(-beta);
+            const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
+            s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
+        }
     }
     if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = u;
     s = fmin(fmax(s, -s_half), s_half);
 
     // The root has the sign of t since t(0) = 0 and t(s) increases.  For
-    // unbound motion the far end of the bracket stays open (+-1e300).
+    // unbound motion the far end of the bracket stays open (+-1e300), except
+    // that an unbound pair moving apart (eta sgn t >= 0) only grows in r, so
+    // t(s) >= r0 s and the root lies within |u|.
     double lo = (t > 0.0) ? 0.0 : -s_half;
     double hi = (t > 0.0) ? s_half : 0.0;
-
-    double G1 = 0.0, G2 = 0.0, G3 = 0.0, r = r0;
-    PairFlow out;
-    out.converged = false;
-    out.safeguarded = false;
-    double ds_prev = 1e300, F_prev = 1e300;
-    int it = 0;
-    while (it < kp.max_iter) {
-        ++it;
-        const double z = beta * s * s;
-        double c2, c3;
-        stumpff23(z, c2, c3);
-        const double s2 = s * s;
-        G1 = s * fma(-z, c3, 1.0);
-        G2 = s2 * c2;
-        G3 = s2 * s * c3;
-        const double G0 = fma(-z, c2, 1.0);
-        const double F = fma(r0, s, fma(eta, G2, fma(zeta, G3, -t)));
-        r = fma(eta, G1, fma(zeta, G2, r0));
-        const double Fpp = fma(eta, G0, zeta * G1);
-        if (F < 0.0) lo = s;
-        else hi = s;
-        const double disc = fma(16.0 * r, r, -20.0 * F * Fpp);
-        const double ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
-        const double ads = fabs(ds), as = fabs(s);
-        // Converged at s: the correction is below tol |s|, or it sits at the
-        // rounding floor of F (tiny and no longer shrinking).
-        if (ads <= kp.tol * as || F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * ds_prev)) {
-            out.converged = true;
-            break;
-        }
-        // Converged at s - ds: the error left after the step, estimated from
-        // the derivatives of t(s) -- the Newton term |t2| ds^2 / 2r and the
-        // cubic terms (|t3| / r + (t2 / r)^2) |ds|^3, with t2, t3 the second and
-        // third derivatives -- is below tol |s - ds| (tested without
-        // divisions).  The G-functions are then carried to s - ds by their
-        // Taylor series (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of
-        // being evaluated again.
-        const double sn_l = s - ds;
-        const double asn = fabs(sn_l);
-        const double aFpp = fabs(Fpp);
-        const double Fppp = fma(zeta, G0, -beta * eta * G1);
-        const double ads2 = ads * ads;
-        const double err_r2 = fma(aFpp * ads2, r, ads2 * ads * fma(fabs(Fppp), r, aFpp * aFpp));
-        if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * kp.tol * asn * r * r &&
-            sn_l >= lo && sn_l <= hi) {
-            const double d = -ds, d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
-            const double mbG1 = -beta * G1, mbG0 = -beta * G0;
-            const double nG3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
-            const double nG2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
-            const double nG1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
-            G1 = nG1;
-            G2 = nG2;
-            G3 = nG3;
-            r = fma(eta, G1, fma(zeta, G2, r0));
-            out.converged = true;
-            break;
-        }
-        ds_prev = ads;
-        double sn = sn_l;
-        // Bisect when the step leaves the bracket or the residual fails to halve
-        // (a slow crawl down an exponential); an open bracket is expanded.
-        const bool stall = fabs(F) > 0.5 * F_prev && ads > 1e-6 * as;
-        if (!(sn >= lo && sn <= hi) || stall) {
-            sn = (hi - lo < 1e299) ? 0.5 * (lo + hi) : 2.0 * s;
-            out.safeguarded = true;
-        }
-        F_prev = fabs(F);
-        s = sn;
+    if (beta <= 0.0 && eta * t >= 0.0) {
+        if (t > 0.0) hi = fmin(hi, u);
+        else lo = fmax(lo, u);
     }
+
+    KepIter st{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
+    // First evaluation in straight-line code; the short Stumpff series when
+    // every lane of the wavefront qualifies.  Almost every pair of a star
+    // cluster converges here.
+    const bool small_z = SAKURA_WAVE_ALL(fabs(beta * s * s) <= 0x1p-10);
+    int res = small_z ? kepler_iterate<true>(st, beta, eta, zeta, r0, t, kp.tol)
+                      : kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    int it = 1;
+    while (res == 0 && it < kp.max_iter) {
+        ++it;
+        res = kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    }
+    PairFlow out;
+    out.converged = res != 0;
+    out.safeguarded = st.safeguarded;
+    const double G1 = st.G1, G2 = st.G2, G3 = st.G3, r = st.r;
     out.iters = it;
     // Lagrange coefficients at the converged s.
     const double rinv = rcp_refined(r);

@@ -92,8 +92,9 @@ __global__ void k_import(int n, int np, const double *__restrict__ m,
 // (DPP wave_rol:1) applied to both halves of a double.
 __device__ inline double from_next_lane(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x134, 0xF, 0xF, false);
+    // every lane has a source under a full rotate, so no "old" value is needed
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -108,7 +109,7 @@ __device__ inline double from_next_lane(double x)
 // s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
 // Partial sums go to part[I][J] (i side) and part[J][I] (j side).
 template <bool HIST>
-__global__ __launch_bounds__(TILE) void k_pairs(int n, int nb, int np, double tau,
+__global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
                                                 double *__restrict__ part,
                                                 DevCounters *cnt, SlotStats *slots,
@@ -263,9 +264,24 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, doubl
     const int c = threadIdx.x / TILE, lane = threadIdx.x % TILE;
     __shared__ double dsum[6][TILE];
     const double *p = part + ((size_t)K * nb * 6 + c) * TILE + lane;
+    const size_t stride = 6 * TILE;
     double s = 0.0, e = 0.0;
-    for (int L = 0; L < nb; ++L) {
-        const double x = p[(size_t)L * 6 * TILE];
+    int L = 0;
+    // eight loads in flight per round; the sum itself stays in order L = 0..nb-1
+    for (; L + 8 <= nb; L += 8) {
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = p[(size_t)(L + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double t = s + x[k];
+            const double bp = t - s;
+            e += (s - (t - bp)) + (x[k] - bp);
+            s = t;
+        }
+    }
+    for (; L < nb; ++L) {
+        const double x = p[(size_t)L * stride];
         const double t = s + x;
         const double bp = t - s;
         e += (s - (t - bp)) + (x - bp);
