@@ -55,6 +55,8 @@ def lib():
         L.sref_num_threads.restype = ctypes.c_int
         L.sref_mlp_forward.argtypes = [_D, ctypes.c_int64, _D, _D]
         L.sref_mlp_loss_grad.argtypes = [_D, ctypes.c_int64, _D, _D, _D, _D]
+        L.sref_guess_sample.argtypes = [ctypes.c_double, ctypes.c_double, _D, _D, _D, _D,
+                                        _D, ctypes.POINTER(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -190,3 +192,19 @@ def mlp_loss_grad(params, x, y):
     if rc:
         raise OracleError(rc, "sref_mlp_loss_grad")
     return float(loss[0]), grad
+
+
+def guess_sample(tau, mu, x0, w0, domain):
+    """Inputs, domain flag and target of the learned Kepler starter for one
+    pair: returns (feat[8], y, in_domain); y is 0 outside the domain."""
+    x0 = _f64(x0, (3,)).copy()
+    w0 = _f64(w0, (3,)).copy()
+    dom = _f64(domain, (4,)).copy()
+    feat = np.empty(8)
+    y = np.empty(1)
+    ind = ctypes.c_int(0)
+    rc = lib().sref_guess_sample(float(tau), float(mu), _p(x0), _p(w0), _p(dom), _p(feat),
+                                 _p(y), ctypes.byref(ind))
+    if rc:
+        raise OracleError(rc, "sref_guess_sample")
+    return feat, float(y[0]), bool(ind.value)

@@ -239,6 +239,65 @@ int sref_kepler(double tau, double mu, const double x0[3], const double w0[3],
 /* Pair map of eq. (26): back-drift tau/2 (eq. 17), Kepler flow tau (eq. 18), */
 /* back-drift tau/2; the increments are the result minus the input.          */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Learned Kepler starter: inputs, domain and target (an extension of the    */
+/* method; the paper's solver only needs some starting value).               */
+/* In units with r0 = 1 and mu = 1 the Kepler problem over time t depends on  */
+/* three numbers only: tau' = |t| sqrt(mu / r0^3), e' = sgn(t) (x0.w0) /      */
+/* sqrt(mu r0) (radial speed over circular speed, sign-flipped for t < 0 by  */
+/* time reversal) and b' = alpha r0 = 2 - r0 |w0|^2 / mu.  The eight inputs   */
+/* are functions of these; the target is y = log(chi r0 / (sqrt(mu) t)), the  */
+/* log of the root over its free-drift value, which is even under time       */
+/* reversal.  Bound orbits use the same period reduction of t as             */
+/* sref_kepler.                                                             */
+/* ------------------------------------------------------------------------ */
+int sref_guess_sample(double tau, double mu, const double x0[3], const double w0[3],
+                      const double domain[4], double feat[8], double *y, int *in_domain)
+{
+    if (!x0 || !w0 || !domain || !feat || !y || !in_domain) return SREF_EINVAL;
+    *in_domain = 0;
+    *y = 0.0;
+    for (int k = 0; k < 8; ++k) feat[k] = 0.0;
+    const double r0 = sqrt(dot3(x0, x0));
+    if (!(r0 > 0.0)) return SREF_ECOLLIDE;
+    if (!(mu > 0.0)) return SREF_OK; /* no Kepler problem: never in the domain */
+    const double sqmu = sqrt(mu);
+    const double alpha = 2.0 / r0 - dot3(w0, w0) / mu;
+    double t = tau;
+    if (alpha > 0.0) {
+        double P = 2.0 * M_PI / (sqmu * alpha * sqrt(alpha));
+        if (fabs(t) > 0.5 * P) t -= P * nearbyint(t / P);
+    }
+    const double sgn = (t > 0.0) ? 1.0 : ((t < 0.0) ? -1.0 : 0.0);
+    const double taup = fabs(t) * sqrt(mu / (r0 * r0 * r0));
+    const double ep = sgn * dot3(x0, w0) / sqrt(mu * r0);
+    const double bp = alpha * r0;
+    const double bpos = bp > 0.0 ? bp : 0.0;
+    feat[0] = (taup > 0.0) ? log2(taup) : -1074.0;
+    feat[1] = ep;
+    feat[2] = bp;
+    feat[3] = taup;
+    feat[4] = ep * taup;
+    feat[5] = taup * taup * (3.0 * ep * ep - 1.0 + bp) / 6.0;
+    feat[6] = taup * bpos * sqrt(bpos);
+    feat[7] = ep * sqrt(bpos);
+    const int dom = taup >= domain[0] && taup <= domain[1] && bp >= domain[2] &&
+                    fabs(ep) <= domain[3];
+    if (!dom) return SREF_OK;
+    kepeq_t k;
+    k.r0 = r0;
+    k.sig0 = dot3(x0, w0) / sqmu;
+    k.alpha = alpha;
+    k.q = 1.0 - alpha * r0;
+    k.T = sqmu * t;
+    double chi;
+    int rc = kepeq_solve(&k, &chi, NULL);
+    if (rc) return rc;
+    *y = log(chi * r0 / (sqmu * t));
+    *in_domain = 1;
+    return SREF_OK;
+}
+
 int sref_pair_increment(double tau, double G, double mi, double mj,
                         const double ri[3], const double vi[3],
                         const double rj[3], const double vj[3], int solver,

@@ -80,6 +80,18 @@ int sref_mlp_forward(const double *params, int64_t batch, const double *x, doubl
 int sref_mlp_loss_grad(const double *params, int64_t batch, const double *x,
                        const double *y, double *loss, double *grad);
 
+/* Inputs and target of the learned Kepler starter for one pair (an extension
+ * of the method, not in the paper).  With t the time after the bound-orbit
+ * period reduction, tau' = |t| sqrt(mu/r0^3), e' = sgn(t) x0.w0 / sqrt(mu r0),
+ * b' = alpha r0:
+ *   feat = {log2 tau', e', b', tau', e' tau', tau'^2 (3 e'^2 - 1 + b') / 6,
+ *           tau' max(b',0)^(3/2), e' max(b',0)^(1/2)}.
+ * domain = {tau_lo, tau_hi, b_lo, e_hi}: the pair is in the domain when
+ * mu > 0, tau_lo <= tau' <= tau_hi, b' >= b_lo and |e'| <= e_hi; only then is
+ * *y = log(chi r0 / (sqrt(mu) t)) computed (chi the converged root). */
+int sref_guess_sample(double tau, double mu, const double x0[3], const double w0[3],
+                      const double domain[4], double feat[8], double *y, int *in_domain);
+
 /* Number of OpenMP threads the row loops use. */
 int sref_num_threads(void);
 
