@@ -72,6 +72,11 @@ typedef struct {
     double call_ms;        /* duration of the whole call on the stream (HIP events) */
     int64_t pair_launches; /* number of pair-kernel launches */
     int64_t failed_step;   /* first failing step, -1 if none */
+    /* Learned starter (zero unless a model is loaded or a harvest is running): */
+    uint64_t guess_domain_pairs; /* solves whose pair lies in the network's domain */
+    uint64_t guess_domain_iters; /* Kepler evaluations of those solves */
+    uint64_t guess_learned;      /* solves started from the network's value */
+    uint64_t guess_restarts;     /* of those, searches restarted from the plain starter */
 } sakura_stats;
 
 /* Create a handle on HIP device `device`; opts may be NULL (defaults).
@@ -118,6 +123,100 @@ int sakura_batch_set_group(sakura_t *h, int n, int lanes);
 int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
                           const double *r, const double *v, const double *dt,
                           int64_t probe_steps, double G, void *stream, double *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Learned Kepler starter (an extension of the method; the paper's solver
+ * needs only some starting value of the universal variable).
+ *
+ * A pair's Kepler problem over time t (after the bound-orbit period
+ * reduction) is fixed, up to scale, by tau' = |t| sqrt(mu/r0^3),
+ * e' = sgn(t) x0.w0 / sqrt(mu r0) and b' = 2 - r0 |w0|^2 / mu.  Pairs with
+ *   domain[0] <= tau' <= domain[1],  b' >= domain[2],  |e'| <= domain[3]
+ * (and mu > 0) are in the network's domain.  The network 8 -> 64 -> 64 -> 1
+ * (ReLU) maps the inputs
+ *   f = {log2 tau', e', b', tau', e' tau', tau'^2 (3 e'^2 - 1 + b') / 6,
+ *        tau' max(b',0)^(3/2), e' max(b',0)^(1/2)},
+ * each as (f[k] - in_shift[k]) * in_scale[k], to y = out_shift + out_scale *
+ * output, and the starter is s = (t / r0) exp(y) in the regularised time
+ * (dt/ds = r); y approximates log(s r0 / t) at the root.  Inference is fused
+ * into the pair kernels on MFMA with bf16 weights and activations and fp32
+ * accumulation, only for wavefronts holding a pair in the domain.  The root
+ * search that follows is the plain one (same stopping rule, same results to
+ * the solver tolerance); a search that fails to converge from the network's
+ * value is restarted from the plain starter.
+ * ------------------------------------------------------------------------- */
+
+#define SAKURA_MLP_PARAMS 4801 /* W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3 */
+#define SAKURA_HARVEST_ROW 12  /* floats per harvest row */
+
+typedef struct {
+    float params[SAKURA_MLP_PARAMS]; /* fp32, packed as listed above (row-major W[out][in]) */
+    float in_shift[8], in_scale[8];
+    float out_shift, out_scale;
+    double domain[4];                /* tau_lo, tau_hi, b_lo, e_hi */
+} sakura_guess_model;
+
+/* Load (copy, HOST pointer) or, with model = NULL, unload the network.  While
+ * a model is loaded, plain-starter runs also count the solves in its domain
+ * (sakura_stats.guess_domain_*).  EINVAL on non-finite values or an empty
+ * domain. */
+int sakura_set_guess_model(sakura_t *h, const sakura_guess_model *model);
+
+/* Starter of later calls: SAKURA_GUESS_ANALYTIC or SAKURA_GUESS_LEARNED (the
+ * latter makes steps fail with ENOMODEL while no model is loaded). */
+int sakura_set_guess(sakura_t *h, int guess);
+
+/* Harvest: until sakura_harvest_end, every step (sakura_step, sakura_evolve,
+ * sakura_batch_evolve) uses the plain starter and appends, for every solved
+ * pair in `domain` (HOST, 4 doubles as above), one row of SAKURA_HARVEST_ROW
+ * floats to `rows` (DEVICE, cap rows): the eight raw inputs f, the target
+ * y = log(s r0 / t) at the converged root, then the particle indices i and j
+ * and the number of Kepler evaluations, those three as int32 bit patterns.
+ * Row order is unspecified.  Rows beyond cap are dropped (but counted). */
+int sakura_harvest_begin(sakura_t *h, float *rows, int64_t cap, const double domain[4]);
+
+/* End the harvest; *offered (HOST, may be NULL) = rows produced, including
+ * those dropped beyond cap. */
+int sakura_harvest_end(sakura_t *h, int64_t *offered);
+
+/* The Kepler root search of the pair kernels on n independent problems
+ * (DEVICE arrays): propagate (x0[k], w0[k]) ([n][3]) with parameter mu[k] over
+ * tau[k], with the handle's starter.  Outputs (DEVICE, [n]): s_start the
+ * starting value, s_root the converged root (regularised time s of t(s)),
+ * info bit 0 in the domain, bit 1 network starter used, bit 2 restarted,
+ * bit 3 converged, bits 8-15 Kepler evaluations.  |x0[k]| must be > 0. */
+int sakura_guess_eval(sakura_t *h, int64_t n, const double *tau, const double *mu,
+                      const double *x0, const double *w0, double *s_start, double *s_root,
+                      int32_t *info, void *stream);
+
+/* Network training kernels (fp32; DEVICE pointers unless noted).
+ * sakura_mlp_forward: out[b] = network output for inputs x[b][8] (already
+ *   shifted and scaled), parameters params[SAKURA_MLP_PARAMS].
+ * sakura_mlp_loss_grad: mean over the batch of (output - y)^2 in *loss (HOST)
+ *   and its gradient in grad[SAKURA_MLP_PARAMS] (same packing as params);
+ *   the per-parameter sums are taken in a fixed order (deterministic). */
+int sakura_mlp_forward(sakura_t *h, const float *params, int64_t batch, const float *x,
+                       float *out, void *stream);
+int sakura_mlp_loss_grad(sakura_t *h, const float *params, int64_t batch, const float *x,
+                         const float *y, float *grad, double *loss, void *stream);
+
+typedef struct {
+    int epochs;          /* passes over the training rows; 0 selects 20 */
+    int batch;           /* minibatch size; 0 selects 4096 */
+    float lr, lr_final;  /* Adam step size, cosine-annealed from lr to lr_final; 0 selects 3e-3, 3e-5 */
+    uint64_t seed;       /* initial weights and minibatch sampling */
+    double val_fraction; /* trailing fraction of the rows held out; 0 selects 0.05 */
+} sakura_fit_opts;
+
+/* Train the starter network on n harvested rows (DEVICE, SAKURA_HARVEST_ROW
+ * floats each) with the kernels above and Adam.  Input and output scaling
+ * come from the training rows' means and standard deviations.  Fills *model
+ * (HOST) including `domain` (HOST, 4 doubles); val_loss (HOST, epochs floats,
+ * may be NULL) receives the held-out mean squared error of the scaled target
+ * after each epoch.  n >= 64 rows. */
+int sakura_mlp_fit(sakura_t *h, const float *rows, int64_t n, const double domain[4],
+                   const sakura_fit_opts *opts, sakura_guess_model *model, float *val_loss,
+                   void *stream);
 
 /* Energy diagnostics of eqs. (1-3) with compensated sums:
  * out[12] (HOST) = {E, K, U, P[3], L[3], Rcm[3]}: total, kinetic and potential

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsakura.so")
-SOURCES = [os.path.join(CSRC, "sakura.hip"), os.path.join(CSRC, "batch.hip")]
+SOURCES = [os.path.join(CSRC, "sakura.hip"), os.path.join(CSRC, "batch.hip"),
+           os.path.join(CSRC, "guess.hip")]
 HEADERS = [os.path.join(CSRC, "kepler_device.hpp"), os.path.join(CSRC, "common.hpp"),
            os.path.join(os.path.dirname(HERE), "include", "sakura.h")]
 

@@ -29,6 +29,9 @@ struct WorkItem {
     int pad;
 };
 
+// MODE selects the starter as in the tile kernel (0 plain, 1 domain
+// statistics, 2 the network's starter, 3 harvest rows).
+template <int MODE>
 __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__restrict__ items,
                                                 const int *__restrict__ order,
                                                 const int64_t *__restrict__ offsets,
@@ -39,12 +42,13 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                                                 double *__restrict__ staged, int64_t ntot,
                                                 long long nsteps,
                                                 double G, DevCounters *cnt, SlotStats *slots,
-                                                kep::KeplerParams kp)
+                                                kep::KeplerParams kp, const kep::GuessNet net)
 {
     __shared__ double sj[7][TILE]; // x y z vx vy vz m of every lane this step
     __shared__ double sa[6][TILE]; // j-side sums
     const int lane = threadIdx.x;
     unsigned n_solve = 0, it_sum = 0, it_max = 0, n_fb = 0;
+    unsigned dom_n = 0, dom_it = 0, n_learned = 0, n_restart = 0; // per lane
 
     for (;;) {
         int item = 0;
@@ -108,9 +112,21 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                 const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
                 const bool collide = act && !(r0sq > 0.0);
                 const bool live = act && !collide;
-                const kep::PairFlow f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0,
-                                                         x0, x1, x2, w0, w1, w2,
-                                                         live ? r0sq : 1.0, kp);
+                kep::PairFlow f;
+                if constexpr (MODE == 0) {
+                    f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
+                                         w1, w2, live ? r0sq : 1.0, kp);
+                } else {
+                    kep::NetGuess<MODE> gp(net, (int)p, (int)(off + ql));
+                    f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
+                                         w1, w2, live ? r0sq : 1.0, kp, gp);
+                    if (live && gp.in_dom) {
+                        ++dom_n;
+                        dom_it += f.iters;
+                    }
+                    n_learned += (live && gp.used) ? 1u : 0u;
+                    n_restart += (live && f.restarted) ? 1u : 0u;
+                }
                 const double a = fma(-h, f.fdot, f.fm1);
                 const double b = fma(-h, f.gdm1, f.gmt);
                 const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
@@ -156,7 +172,42 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
     it_sum = wave_sum(it_sum);
     n_fb = wave_sum(n_fb);
     it_max = wave_max(it_max);
-    if (lane == 0) slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+    GuessCount gc;
+    if (MODE != 0) {
+        gc.dom = wave_sum(dom_n);
+        gc.dom_iters = wave_sum(dom_it);
+        gc.learned = wave_sum(n_learned);
+        gc.restarts = wave_sum(n_restart);
+    }
+    if (lane == 0) {
+        slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+        if (MODE != 0) slot_add_guess(slots, blockIdx.x, gc);
+    }
+}
+
+void launch_batch(int mode, int grid, hipStream_t st, int nitems, const WorkItem *items,
+                  const int *order, const int64_t *offsets, const double *m, const double *r,
+                  const double *v, const double *dt, double *staged, int64_t ntot,
+                  long long nsteps, double G, DevCounters *cnt, SlotStats *slots,
+                  kep::KeplerParams kp, const kep::GuessNet &net)
+{
+    switch (mode) {
+    case 1:
+        k_batch<1><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
+                                          nsteps, G, cnt, slots, kp, net);
+        break;
+    case 2:
+        k_batch<2><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
+                                          nsteps, G, cnt, slots, kp, net);
+        break;
+    case 3:
+        k_batch<3><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
+                                          nsteps, G, cnt, slots, kp, net);
+        break;
+    default:
+        k_batch<0><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
+                                          nsteps, G, cnt, slots, kp, net);
+    }
 }
 
 // Staged results -> caller arrays, only when every system and step succeeded.
@@ -269,6 +320,9 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     const int grid = std::max(1, std::min(nitems, cus * std::max(1, h->batch_waves_per_cu)));
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
+    kep::GuessNet net{};
+    const int mode = guess_mode(h, &net);
+    if (mode < 0) return fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
     const WorkItem *witems = reinterpret_cast<const WorkItem *>(h->batch_work);
     const int *worder = h->batch_work + 4 * nitems;
     const unsigned eblocks = (unsigned)((3 * ntot + 255) / 256);
@@ -276,10 +330,11 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     // The launch sequence is captured once into a graph (on a private stream)
     // and replayed while the arguments stay the same.
     char keybuf[512];
-    std::snprintf(keybuf, sizeof(keybuf), "%p %p %p %p %p %p %lld %lld %a %d %d %a %d",
+    std::snprintf(keybuf, sizeof(keybuf), "%p %p %p %p %p %p %lld %lld %a %d %d %a %d %d %u %p %lld %a %a %a %a",
                   (const void *)m, (void *)r, (void *)v, (const void *)dt,
                   (void *)h->batch_state, (void *)h->batch_work, (long long)nsys,
-                  (long long)nsteps, G, nitems, grid, kp.tol, kp.max_iter);
+                  (long long)nsteps, G, nitems, grid, kp.tol, kp.max_iter, mode, h->model_gen,
+                  (void *)net.rows, net.row_cap, net.tau2_lo, net.tau2_hi, net.b_lo, net.e2_hi);
     const bool use_graph = !h->batch_no_graph;
     if (use_graph && (h->graph_exec == nullptr || h->graph_key != keybuf)) {
         if (h->graph_exec) {
@@ -294,9 +349,9 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
             SAKURA_HIP(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
         SAKURA_HIP(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
         k_clear<<<1, NSLOT, 0, h->capture_stream>>>(h->cnt, h->slots);
-        k_batch<<<grid, TILE, 0, h->capture_stream>>>(nitems, witems, worder, h->batch_offsets, m,
-                                                      r, v, dt, h->batch_state, ntot,
-                                                      (long long)nsteps, G, h->cnt, h->slots, kp);
+        launch_batch(mode, grid, h->capture_stream, nitems, witems, worder, h->batch_offsets, m,
+                     r, v, dt, h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp,
+                     net);
         k_batch_export<<<eblocks, 256, 0, h->capture_stream>>>(ntot, h->batch_state, r, v,
                                                                h->cnt);
         k_fold_stats<<<1, NSLOT, 0, h->capture_stream>>>(h->slots, h->cnt);
@@ -309,9 +364,8 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         SAKURA_HIP(h, hipGraphLaunch(h->graph_exec, st));
     } else {
         k_clear<<<1, NSLOT, 0, st>>>(h->cnt, h->slots);
-        k_batch<<<grid, TILE, 0, st>>>(nitems, witems, worder, h->batch_offsets, m, r, v, dt,
-                                       h->batch_state, ntot, (long long)nsteps, G, h->cnt,
-                                       h->slots, kp);
+        launch_batch(mode, grid, st, nitems, witems, worder, h->batch_offsets, m, r, v, dt,
+                     h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
         k_batch_export<<<eblocks, 256, 0, st>>>(ntot, h->batch_state, r, v, h->cnt);
         k_fold_stats<<<1, NSLOT, 0, st>>>(h->slots, h->cnt);
         SAKURA_HIP(h, hipGetLastError());
@@ -326,6 +380,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         stats->iters_total = c.iters_total;
         stats->fallbacks = c.fallbacks;
         stats->iters_max = c.iters_max;
+        guess_stats(c, stats);
         stats->pair_launches = 1;
         stats->failed_step = c.status ? c.failed_step : -1;
         float ms = 0.0f;

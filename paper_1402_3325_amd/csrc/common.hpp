@@ -13,6 +13,7 @@
 
 #include "../../include/sakura.h"
 #include "kepler_device.hpp"
+#include "guess_device.hpp"
 
 namespace sk {
 
@@ -29,6 +30,8 @@ struct DevCounters {
     long long failed_step;
     unsigned hist[32];
     unsigned work_next; // work-queue head of the batched kernel
+    unsigned long long dom_pairs, dom_iters; // solves in the starter network's domain
+    unsigned long long learned, restarts;    // network starters used; restarts from the plain one
 };
 
 // Iteration statistics are added into NSLOT counter slots of one cache line
@@ -38,7 +41,10 @@ constexpr int NSLOT = 1024;
 struct SlotStats {
     unsigned long long pair_solves, iters_total, fallbacks;
     unsigned iters_max;
-    unsigned pad[9];
+    unsigned learned, restarts;
+    unsigned pad;
+    unsigned long long dom_pairs, dom_iters;
+    unsigned long long pad2;
 };
 static_assert(sizeof(SlotStats) == 64, "one cache line per slot");
 
@@ -50,6 +56,24 @@ __device__ inline void slot_add(SlotStats *slots, unsigned block, unsigned long 
     atomicAdd(&sl->iters_total, iters);
     atomicAdd(&sl->fallbacks, fb);
     atomicMax(&sl->iters_max, imax);
+}
+
+// Starter statistics: solves in the network's domain and their evaluations,
+// network starters used, restarts from the plain starter.
+struct GuessCount {
+    unsigned long long dom = 0, dom_iters = 0;
+    unsigned learned = 0, restarts = 0;
+};
+
+__device__ inline void slot_add_guess(SlotStats *slots, unsigned block, const GuessCount &g)
+{
+    SlotStats *sl = slots + (block & (NSLOT - 1));
+    if (g.dom) {
+        atomicAdd(&sl->dom_pairs, g.dom);
+        atomicAdd(&sl->dom_iters, g.dom_iters);
+    }
+    if (g.learned) atomicAdd(&sl->learned, g.learned);
+    if (g.restarts) atomicAdd(&sl->restarts, g.restarts);
 }
 
 __device__ inline unsigned wave_sum(unsigned x)
@@ -116,6 +140,20 @@ struct sakura {
     int64_t cap_tune = 0;
     int batch_waves_per_cu = 8;
     int batch_no_graph = 0;
+    // learned starter
+    void *net_buf = nullptr;      // packed bf16 fragments and fp32 vectors of the network
+    bool has_model = false;
+    unsigned model_gen = 0;       // bumped by every model load (graph keys)
+    kep::GuessNet net{};          // the loaded network (domain of the model)
+    // harvest
+    bool harvesting = false;
+    kep::GuessNet harvest{};      // domain and row buffer of the harvest
+    unsigned long long *row_count = nullptr;
+    // network training scratch
+    float *mlp_buf = nullptr;
+    int64_t cap_mlp = 0;
+    double *mlp_part = nullptr;
+    int64_t cap_mlp_part = 0;
 };
 
 namespace sk {
@@ -150,6 +188,36 @@ int grow(sakura_t *h, T **buf, int64_t *cap, int64_t need)
     }
     *cap = need;
     return SAKURA_OK;
+}
+
+// Starter mode of the next launch: -1 learned requested without a model,
+// 0 plain, 1 plain with domain statistics (a model is loaded), 2 the
+// network's starter, 3 harvest.  *net receives the kernel argument.
+inline int guess_mode(const sakura_t *h, kep::GuessNet *net)
+{
+    if (h->harvesting) {
+        *net = h->harvest;
+        return 3;
+    }
+    if (h->opts.guess == SAKURA_GUESS_LEARNED) {
+        if (!h->has_model) return -1;
+        *net = h->net;
+        return 2;
+    }
+    if (h->has_model) {
+        *net = h->net;
+        return 1;
+    }
+    *net = kep::GuessNet{};
+    return 0;
+}
+
+inline void guess_stats(const DevCounters &c, sakura_stats *st)
+{
+    st->guess_domain_pairs = c.dom_pairs;
+    st->guess_domain_iters = c.dom_iters;
+    st->guess_learned = c.learned;
+    st->guess_restarts = c.restarts;
 }
 
 inline int status_code(unsigned st)

@@ -121,6 +121,7 @@ struct PairFlow {
     int iters;
     bool converged;
     bool safeguarded; // a bisection or bracket-expansion step was needed
+    bool restarted;   // the search was started again from the plain starter
 };
 
 // State of the root search on t(s) = tau.
@@ -212,11 +213,77 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     return 0;
 }
 
+// Plain starter and bracket of the root search on t(s) = t.
+//
+// Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  When its
+// corrections dominate the series is no guide: start from the free drift u
+// instead, or, deep in the hyperbolic regime (-beta u^2 > 1), from the
+// inversion of t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3), k = sqrt(-beta).
+//
+// Bracket: the root has the sign of t since t(0) = 0 and t(s) increases.  For
+// unbound motion the far end stays open (+-1e300), except that an unbound pair
+// moving apart (eta sgn t >= 0) only grows in r, so t(s) >= r0 s and the root
+// lies within |u|.
+SAKURA_HD inline void analytic_start(double t, double u, double r0, double r0inv, double eta,
+                                     double zeta, double beta, double mu, double s_half,
+                                     double &s, double &lo, double &hi)
+{
+    const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
+    const double corr1 = -0.5 * eta * r0inv * u, corr2 = c3s * u * u;
+    s = u * (1.0 + corr1 + corr2);
+    if (fabs(corr1) + fabs(corr2) > 0.5) {
+        s = u;
+        if (beta < 0.0 && -beta * u * u > 1.0) {
+            const double k = sqrt(-beta);
+            const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
+            s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
+        }
+    }
+    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = u;
+    s = fmin(fmax(s, -s_half), s_half);
+    lo = (t > 0.0) ? 0.0 : -s_half;
+    hi = (t > 0.0) ? s_half : 0.0;
+    if (beta <= 0.0 && eta * t >= 0.0) {
+        if (t > 0.0) hi = fmin(hi, u);
+        else lo = fmax(lo, u);
+    }
+}
+
+// A starter policy sees every pair between the plain starter and the root
+// search (all lanes of the wavefront together) and again after the search.
+// NoGuess keeps the plain starter.
+struct NoGuess {
+    static constexpr bool active = false;
+    SAKURA_HD bool start(double, double, double, double, double, double, double, double,
+                         double, double &) { return false; }
+    SAKURA_HD void done(double, double, double, double, double, double, double, int) {}
+};
+
+// Root search from st until convergence or kp.max_iter evaluations; the first
+// evaluation uses the short Stumpff series when every lane of the wavefront
+// qualifies (almost every pair of a star cluster converges there).
+SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double zeta, double r0,
+                                   double t, const KeplerParams &kp, int &it)
+{
+    const bool small_z = SAKURA_WAVE_ALL(fabs(beta * st.s * st.s) <= 0x1p-10);
+    int res = small_z ? kepler_iterate<true>(st, beta, eta, zeta, r0, t, kp.tol)
+                      : kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    it = 1;
+    while (res == 0 && it < kp.max_iter) {
+        ++it;
+        res = kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    }
+    return res;
+}
+
 // Kepler flow over tau of the relative state (x0, w0) with parameter mu >= 0
 // and r0^2 = |x0|^2 > 0 (callers substitute a trivial problem otherwise).
-SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1,
-                                      double x2, double w0, double w1, double w2,
-                                      double r0sq, const KeplerParams &kp)
+// With a starter policy that replaced the plain starter, a search that fails
+// to converge is started again from the plain starter (PairFlow::restarted).
+template <class Guess>
+SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1, double x2,
+                                      double w0, double w1, double w2, double r0sq,
+                                      const KeplerParams &kp, Guess &guess)
 {
     const double r0inv = rsqrt_refined(r0sq);
     const double r0 = r0sq * r0inv;
@@ -235,55 +302,32 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         const double P = 6.283185307179586 * mu * ib * ib * ib;
         if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
     }
-
-    // Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  When
-    // its corrections dominate the series is no guide: start from the free
-    // drift u instead, or, deep in the hyperbolic regime (-beta u^2 > 1), from
-    // the inversion of t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3),
-    // k = sqrt(-beta).
     const double u = t * r0inv;
-    const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
-    const double corr1 = -0.5 * eta * r0inv * u, corr2 = c3s * u * u;
-    double s = u * (1.0 + corr1 + corr2);
-    if (fabs(corr1) + fabs(corr2) > 0.5) {
-        s = u;
-        if (beta < 0.0 && -beta * u * u > 1.0) {
-            const double k = sqrt(-beta);
-            const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
-            s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
-        }
-    }
-    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = u;
-    s = fmin(fmax(s, -s_half), s_half);
-
-    // The root has the sign of t since t(0) = 0 and t(s) increases.  For
-    // unbound motion the far end of the bracket stays open (+-1e300), except
-    // that an unbound pair moving apart (eta sgn t >= 0) only grows in r, so
-    // t(s) >= r0 s and the root lies within |u|.
-    double lo = (t > 0.0) ? 0.0 : -s_half;
-    double hi = (t > 0.0) ? s_half : 0.0;
-    if (beta <= 0.0 && eta * t >= 0.0) {
-        if (t > 0.0) hi = fmin(hi, u);
-        else lo = fmax(lo, u);
-    }
+    double s, lo, hi;
+    analytic_start(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, s, lo, hi);
+    bool replaced = false;
+    if (Guess::active) replaced = guess.start(t, mu, r0, r0inv, eta, beta, u, lo, hi, s);
 
     KepIter st{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
-    // First evaluation in straight-line code; the short Stumpff series when
-    // every lane of the wavefront qualifies.  Almost every pair of a star
-    // cluster converges here.
-    const bool small_z = SAKURA_WAVE_ALL(fabs(beta * s * s) <= 0x1p-10);
-    int res = small_z ? kepler_iterate<true>(st, beta, eta, zeta, r0, t, kp.tol)
-                      : kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
-    int it = 1;
-    while (res == 0 && it < kp.max_iter) {
-        ++it;
-        res = kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    int it = 0;
+    int res = kepler_search(st, beta, eta, zeta, r0, t, kp, it);
+    bool restarted = false;
+    if (Guess::active && res == 0 && replaced) {
+        restarted = true;
+        const double sh = beta > 0.0 ? 6.3 * rsqrt_refined(beta) : 1e300;
+        analytic_start(t, t * r0inv, r0, r0inv, eta, zeta, beta, mu, sh, s, lo, hi);
+        st = KepIter{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
+        int it2 = 0;
+        res = kepler_search(st, beta, eta, zeta, r0, t, kp, it2);
+        it += it2;
     }
     PairFlow out;
     out.converged = res != 0;
     out.safeguarded = st.safeguarded;
+    out.restarted = restarted;
     const double G1 = st.G1, G2 = st.G2, G3 = st.G3, r = st.r;
     out.iters = it;
+    if (Guess::active) guess.done(st.s, t, mu, r0, r0inv, eta, beta, it);
     // Lagrange coefficients at the converged s.
     const double rinv = rcp_refined(r);
     out.fm1 = -mu * G2 * r0inv;
@@ -291,6 +335,14 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
     out.fdot = -mu * G1 * rinv * r0inv;
     out.gdm1 = -mu * G2 * rinv;
     return out;
+}
+
+SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1, double x2,
+                                      double w0, double w1, double w2, double r0sq,
+                                      const KeplerParams &kp)
+{
+    NoGuess g;
+    return kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
 }
 
 } // namespace kep

@@ -18,6 +18,10 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
     slots[t].iters_total = 0;
     slots[t].fallbacks = 0;
     slots[t].iters_max = 0;
+    slots[t].learned = 0;
+    slots[t].restarts = 0;
+    slots[t].dom_pairs = 0;
+    slots[t].dom_iters = 0;
     if (t == 0) {
         c->status = 0;
         c->iters_max = 0;
@@ -26,35 +30,53 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
         c->fallbacks = 0;
         c->failed_step = LLONG_MAX;
         c->work_next = 0;
+        c->dom_pairs = 0;
+        c->dom_iters = 0;
+        c->learned = 0;
+        c->restarts = 0;
     }
     if (t < 32) c->hist[t] = 0;
 }
 
-// Sum of the counter slots (fixed order, one workgroup of NSLOT threads).
-__global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
+namespace {
+// Sum (or maximum) over the NSLOT threads of one workgroup, fixed order.
+__device__ unsigned long long fold_slots(unsigned long long *a, unsigned long long x, bool is_max)
 {
-    __shared__ unsigned long long a[NSLOT], b[NSLOT], f[NSLOT];
-    __shared__ unsigned mx[NSLOT];
     const int t = threadIdx.x;
-    a[t] = slots[t].pair_solves;
-    b[t] = slots[t].iters_total;
-    f[t] = slots[t].fallbacks;
-    mx[t] = slots[t].iters_max;
     __syncthreads();
-    for (int w = NSLOT / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            a[t] += a[t + w];
-            b[t] += b[t + w];
-            f[t] += f[t + w];
-            mx[t] = max(mx[t], mx[t + w]);
-        }
+    a[t] = x;
+    __syncthreads();
+    for (int w = sk::NSLOT / 2; w > 0; w >>= 1) {
+        if (t < w) a[t] = is_max ? max(a[t], a[t + w]) : a[t] + a[t + w];
         __syncthreads();
     }
+    return a[0];
+}
+} // namespace
+
+// Sum of the counter slots (one workgroup of NSLOT threads).
+__global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
+{
+    __shared__ unsigned long long a[NSLOT];
+    const int t = threadIdx.x;
+    const SlotStats sl = slots[t];
+    const unsigned long long solves = fold_slots(a, sl.pair_solves, false);
+    const unsigned long long iters = fold_slots(a, sl.iters_total, false);
+    const unsigned long long fb = fold_slots(a, sl.fallbacks, false);
+    const unsigned long long mx = fold_slots(a, sl.iters_max, true);
+    const unsigned long long dom = fold_slots(a, sl.dom_pairs, false);
+    const unsigned long long dit = fold_slots(a, sl.dom_iters, false);
+    const unsigned long long lrn = fold_slots(a, sl.learned, false);
+    const unsigned long long rst = fold_slots(a, sl.restarts, false);
     if (t == 0) {
-        c->pair_solves = a[0];
-        c->iters_total = b[0];
-        c->fallbacks = f[0];
-        c->iters_max = mx[0];
+        c->pair_solves = solves;
+        c->iters_total = iters;
+        c->fallbacks = fb;
+        c->iters_max = (unsigned)mx;
+        c->dom_pairs = dom;
+        c->dom_iters = dit;
+        c->learned = lrn;
+        c->restarts = rst;
     }
 }
 
@@ -108,12 +130,15 @@ __device__ inline double from_next_lane(double x)
 // LDS writes and no barrier inside the loop.  The diagonal tile runs
 // s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
 // Partial sums go to part[I][J] (i side) and part[J][I] (j side).
-template <bool HIST>
+// MODE selects the starter: 0 plain; with a loaded network 1 plain with
+// domain statistics, 2 the network's starter, 3 plain with harvest rows.
+template <bool HIST, int MODE>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
                                                 double *__restrict__ part,
                                                 DevCounters *cnt, SlotStats *slots,
-                                                kep::KeplerParams kp, long long step)
+                                                kep::KeplerParams kp, long long step,
+                                                const kep::GuessNet net)
 {
     if (cnt->status) return; // an earlier failure: the call will report it
     const int t = blockIdx.x;
@@ -166,6 +191,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     double jac[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // sums of slot (lane + s) mod 64
     unsigned it_sum = 0, it_max = 0;          // per lane
     unsigned long long n_solve = 0, n_fb = 0; // per wave (ballot counts)
+    GuessCount gc;                            // per wave
+    unsigned dom_it = 0;                      // per lane
     bool any_noconv = false, any_collide = false;
     __syncthreads();
 
@@ -188,9 +215,22 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const bool collide = act && !(r0sq > 0.0);
         const bool live = act && !collide;
         // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
-        const kep::PairFlow f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0,
-                                                 x0, x1, x2, w0, w1, w2,
-                                                 live ? r0sq : 1.0, kp);
+        kep::PairFlow f;
+        if constexpr (MODE == 0) {
+            f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                                 w2, live ? r0sq : 1.0, kp);
+        } else {
+            kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
+            f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                                 w2, live ? r0sq : 1.0, kp, gp);
+            const bool dom = live && gp.in_dom;
+            gc.dom += __popcll(__ballot(dom));
+            dom_it += dom ? (unsigned)f.iters : 0u;
+            if (MODE == 2) {
+                gc.learned += __popcll(__ballot(live && gp.used));
+                gc.restarts += __popcll(__ballot(live && f.restarted));
+            }
+        }
         // the same relative state again, from LDS (bitwise equal to the above)
         asm volatile("" ::: "memory");
         w0 = si[3][lane] - sj[3][q];
@@ -244,9 +284,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
 
     it_sum = wave_sum(it_sum);
     it_max = wave_max(it_max);
+    if (MODE != 0) gc.dom_iters = wave_sum(dom_it);
     const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
     if (lane == 0) {
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+        if (MODE != 0) slot_add_guess(slots, blockIdx.x, gc);
         if (flags) record_error(cnt, flags, step);
     }
     if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
@@ -424,6 +466,34 @@ __global__ void k_energy_final(int ntiles, int nblk, double G, const double *__r
     }
 }
 
+template <bool HIST>
+void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
+                    double G, const double *S, double *part, DevCounters *cnt, SlotStats *slots,
+                    kep::KeplerParams kp, long long step, const kep::GuessNet &net)
+{
+    switch (mode) {
+    case 1:
+        k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        break;
+    case 2:
+        k_pairs<HIST, 2><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        break;
+    case 3:
+        k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        break;
+    default:
+        k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+    }
+}
+
+void launch_pairs(bool hist, int mode, int ntiles, hipStream_t st, int n, int nb, int np,
+                  double dt, double G, const double *S, double *part, DevCounters *cnt,
+                  SlotStats *slots, kep::KeplerParams kp, long long step, const kep::GuessNet &net)
+{
+    if (hist) launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+    else launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+}
+
 int need_events(sakura_t *h, size_t count)
 {
     while (h->events.size() < count) {
@@ -450,9 +520,9 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     if (opts) h->opts = *opts;
     if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = 0x1p-50;
     if (h->opts.max_iter <= 0) h->opts.max_iter = 40;
-    if (h->opts.guess != SAKURA_GUESS_ANALYTIC) {
+    if (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED) {
         delete h;
-        return SAKURA_ENOMODEL;
+        return SAKURA_EINVAL;
     }
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc((void **)&h->cnt, sizeof(sk::DevCounters)) != hipSuccess ||
@@ -482,6 +552,10 @@ void sakura_destroy(sakura_t *h)
     if (h->batch_work) (void)hipFree(h->batch_work);
     if (h->batch_offsets) (void)hipFree(h->batch_offsets);
     if (h->tune_rv) (void)hipFree(h->tune_rv);
+    if (h->net_buf) (void)hipFree(h->net_buf);
+    if (h->row_count) (void)hipFree(h->row_count);
+    if (h->mlp_buf) (void)hipFree(h->mlp_buf);
+    if (h->mlp_part) (void)hipFree(h->mlp_part);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
@@ -519,18 +593,17 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     const double half = 0.5 * dt;
     const int ntiles = nb * (nb + 1) / 2;
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
+    kep::GuessNet net{};
+    const int mode = sk::guess_mode(h, &net);
+    if (mode < 0) return sk::fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
     sk::k_clear<<<1, sk::NSLOT, 0, st>>>(h->cnt, h->slots);
     k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, half, h->state, h->cnt);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * s], st));
-        if (h->opts.histogram)
-            k_pairs<true><<<ntiles, sk::TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
-                                                   h->cnt, h->slots, kp, s);
-        else
-            k_pairs<false><<<ntiles, sk::TILE, 0, st>>>((int)n, nb, np, dt, G, h->state, h->part,
-                                                    h->cnt, h->slots, kp, s);
+        launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, dt, G, h->state,
+                     h->part, h->cnt, h->slots, kp, s, net);
         if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * s], st));
         k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, half, h->state, h->part, h->cnt, s);
     }
@@ -547,6 +620,7 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
         stats->iters_total = c.iters_total;
         stats->fallbacks = c.fallbacks;
         stats->iters_max = c.iters_max;
+        sk::guess_stats(c, stats);
         for (int k = 0; k < 32; ++k) stats->hist[k] = c.hist[k];
         stats->pair_launches = nsteps;
         stats->failed_step = c.status ? c.failed_step : -1;

@@ -37,12 +37,53 @@ class Stats(ctypes.Structure):
                 ("fallbacks", ctypes.c_uint64), ("iters_max", ctypes.c_uint32),
                 ("hist", ctypes.c_uint32 * 32), ("pair_kernel_ms", ctypes.c_double),
                 ("call_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64),
-                ("failed_step", ctypes.c_int64)]
+                ("failed_step", ctypes.c_int64), ("guess_domain_pairs", ctypes.c_uint64),
+                ("guess_domain_iters", ctypes.c_uint64), ("guess_learned", ctypes.c_uint64),
+                ("guess_restarts", ctypes.c_uint64)]
 
     def to_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "hist"}
         d["hist"] = list(self.hist)
         return d
+
+
+MLP_PARAMS = 4801
+HARVEST_ROW = 12
+
+
+class GuessModel(ctypes.Structure):
+    """sakura_guess_model: fp32 parameters W1[64][8], b1, W2[64][64], b2, W3, b3,
+    input/output scaling and the domain {tau_lo, tau_hi, b_lo, e_hi}."""
+    _fields_ = [("params", ctypes.c_float * MLP_PARAMS), ("in_shift", ctypes.c_float * 8),
+                ("in_scale", ctypes.c_float * 8), ("out_shift", ctypes.c_float),
+                ("out_scale", ctypes.c_float), ("domain", ctypes.c_double * 4)]
+
+    def to_dict(self):
+        import numpy as np
+        return {"params": np.ctypeslib.as_array(self.params).copy(),
+                "in_shift": list(self.in_shift), "in_scale": list(self.in_scale),
+                "out_shift": self.out_shift, "out_scale": self.out_scale,
+                "domain": list(self.domain)}
+
+    @classmethod
+    def from_dict(cls, d):
+        m = cls()
+        for k, v in enumerate(d["params"]):
+            m.params[k] = float(v)
+        for k in range(8):
+            m.in_shift[k] = float(d["in_shift"][k])
+            m.in_scale[k] = float(d["in_scale"][k])
+        m.out_shift = float(d["out_shift"])
+        m.out_scale = float(d["out_scale"])
+        for k in range(4):
+            m.domain[k] = float(d["domain"][k])
+        return m
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("val_fraction", ctypes.c_double)]
 
 
 def declared_functions():
@@ -84,6 +125,20 @@ def load_library():
     L.sakura_autotune_batch.restype = ctypes.c_int
     L.sakura_last_error.argtypes = [P]
     L.sakura_last_error.restype = ctypes.c_char_p
+    D4 = ctypes.POINTER(ctypes.c_double)
+    L.sakura_set_guess_model.argtypes = [P, ctypes.POINTER(GuessModel)]
+    L.sakura_set_guess.argtypes = [P, ctypes.c_int]
+    L.sakura_harvest_begin.argtypes = [P, P, ctypes.c_int64, D4]
+    L.sakura_harvest_end.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    L.sakura_guess_eval.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, P]
+    L.sakura_mlp_forward.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    L.sakura_mlp_loss_grad.argtypes = [P, P, ctypes.c_int64, P, P, P, D4, P]
+    L.sakura_mlp_fit.argtypes = [P, P, ctypes.c_int64, D4, ctypes.POINTER(FitOpts),
+                                 ctypes.POINTER(GuessModel), ctypes.POINTER(ctypes.c_float), P]
+    for f in ("sakura_set_guess_model", "sakura_set_guess", "sakura_harvest_begin",
+              "sakura_harvest_end", "sakura_guess_eval", "sakura_mlp_forward",
+              "sakura_mlp_loss_grad", "sakura_mlp_fit"):
+        getattr(L, f).restype = ctypes.c_int
     return L
 
 
@@ -223,3 +278,90 @@ class Sakura:
             self._raise(rc)
         o = list(out)
         return {"E": o[0], "K": o[1], "U": o[2], "P": o[3:6], "L": o[6:9], "Rcm": o[9:12]}
+
+    # ---- learned Kepler starter -------------------------------------------
+
+    def _ok(self, rc):
+        if rc != OK:
+            self._raise(rc)
+
+    def set_guess_model(self, model):
+        """Load a GuessModel (or a dict from GuessModel.to_dict); None unloads."""
+        if model is None:
+            self._ok(self._lib.sakura_set_guess_model(self._h, None))
+            return
+        if isinstance(model, dict):
+            model = GuessModel.from_dict(model)
+        self._ok(self._lib.sakura_set_guess_model(self._h, ctypes.byref(model)))
+
+    def set_guess(self, guess: int):
+        self._ok(self._lib.sakura_set_guess(self._h, int(guess)))
+
+    def harvest_begin(self, rows, domain):
+        """Start recording harvest rows into `rows` (CUDA float32 [cap, 12])."""
+        import torch
+        if not (isinstance(rows, torch.Tensor) and rows.dtype == torch.float32 and rows.is_cuda
+                and rows.is_contiguous() and rows.dim() == 2 and rows.shape[1] == HARVEST_ROW):
+            raise TypeError("rows must be a contiguous CUDA float32 tensor [cap, 12]")
+        dom = (ctypes.c_double * 4)(*[float(x) for x in domain])
+        self._ok(self._lib.sakura_harvest_begin(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                                rows.shape[0], dom))
+
+    def harvest_end(self):
+        """Stop recording; returns the number of rows produced (including any
+        dropped beyond the buffer's capacity)."""
+        c = ctypes.c_int64(0)
+        self._ok(self._lib.sakura_harvest_end(self._h, ctypes.byref(c)))
+        return c.value
+
+    def guess_eval(self, tau, mu, x0, w0):
+        """The pair kernels' root search on independent problems (CUDA float64
+        tau [n], mu [n], x0 [n, 3], w0 [n, 3]).  Returns (s_start, s_root, info)."""
+        import torch
+        n = tau.shape[0]
+        for t in (tau, mu, x0, w0):
+            if not (t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()):
+                raise TypeError("inputs must be contiguous CUDA float64 tensors")
+        if tuple(mu.shape) != (n,) or tuple(x0.shape) != (n, 3) or tuple(w0.shape) != (n, 3):
+            raise ValueError("shapes must be tau [n], mu [n], x0 [n, 3], w0 [n, 3]")
+        s0 = torch.empty(n, dtype=torch.float64, device=tau.device)
+        s1 = torch.empty_like(s0)
+        info = torch.empty(n, dtype=torch.int32, device=tau.device)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+        self._ok(self._lib.sakura_guess_eval(self._h, n, ptr(tau), ptr(mu), ptr(x0), ptr(w0),
+                                             ptr(s0), ptr(s1), ptr(info), self._stream(tau)))
+        return s0, s1, info
+
+    def mlp_forward(self, params, x):
+        """Network output (fp32 training kernels) for scaled inputs x [b, 8]."""
+        import torch
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._ok(self._lib.sakura_mlp_forward(self._h, ctypes.c_void_p(params.data_ptr()),
+                                              x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr()), self._stream(x)))
+        return out
+
+    def mlp_loss_grad(self, params, x, y):
+        """Mean squared error and its gradient (fp32 training kernels)."""
+        import torch
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double(0.0)
+        self._ok(self._lib.sakura_mlp_loss_grad(
+            self._h, ctypes.c_void_p(params.data_ptr()), x.shape[0],
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(grad.data_ptr()), ctypes.byref(loss), self._stream(x)))
+        return loss.value, grad
+
+    def mlp_fit(self, rows, domain, epochs=20, batch=4096, lr=3e-3, lr_final=3e-5, seed=1,
+                val_fraction=0.05):
+        """Train the starter network on harvested rows (CUDA float32 [n, 12]).
+        Returns (GuessModel, list of held-out losses per epoch)."""
+        model = GuessModel()
+        o = FitOpts(int(epochs), int(batch), float(lr), float(lr_final), int(seed),
+                    float(val_fraction))
+        dom = (ctypes.c_double * 4)(*[float(x) for x in domain])
+        hist = (ctypes.c_float * max(1, int(epochs)))()
+        self._ok(self._lib.sakura_mlp_fit(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                          rows.shape[0], dom, ctypes.byref(o),
+                                          ctypes.byref(model), hist, self._stream(rows)))
+        return model, list(hist)

@@ -44,3 +44,31 @@ def test_product_path_never_loads_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "sref_" not in src, f
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of every struct in include/sakura.h, as gcc lays
+    them out, against the ctypes mirrors of the binding."""
+    import subprocess
+    fields = {"sakura_opts": sakura.Opts, "sakura_stats": sakura.Stats,
+              "sakura_guess_model": sakura.GuessModel, "sakura_fit_opts": sakura.FitOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sakura.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
