@@ -117,7 +117,14 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                     f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
                                          w1, w2, live ? r0sq : 1.0, kp);
                 } else {
-                    kep::NetGuess<MODE> gp(net, (int)p, (int)(off + ql));
+                    double s_net = __builtin_nan("");
+                    if (MODE == 2) {
+                        const bool cand = live && kep::pair_may_qualify(net, tau, G * msum, r0sq);
+                        if (__any(cand))
+                            s_net = kep::net_starter(net, tau, cand ? G * msum : 0.0, x0, x1, x2,
+                                                     w0, w1, w2, r0sq);
+                    }
+                    kep::NetGuess<MODE> gp(net, (int)p, (int)(off + ql), s_net);
                     f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
                                          w1, w2, live ? r0sq : 1.0, kp, gp);
                     if (live && gp.in_dom) {

@@ -32,6 +32,7 @@ struct DevCounters {
     unsigned work_next; // work-queue head of the batched kernel
     unsigned long long dom_pairs, dom_iters; // solves in the starter network's domain
     unsigned long long learned, restarts;    // network starters used; restarts from the plain one
+    unsigned defer_ntiles, defer_next;       // deferred-pair list of the current step
 };
 
 // Iteration statistics are added into NSLOT counter slots of one cache line
@@ -142,6 +143,10 @@ struct sakura {
     int batch_no_graph = 0;
     // learned starter
     void *net_buf = nullptr;      // packed bf16 fragments and fp32 vectors of the network
+    int2 *defer_pairs = nullptr;  // deferred-pair lists of the tile kernel
+    int64_t cap_defer = 0;
+    int *defer_idx = nullptr;     // per-tile counts, then the compact tile list
+    int64_t cap_defer_idx = 0;
     bool has_model = false;
     unsigned model_gen = 0;       // bumped by every model load (graph keys)
     kep::GuessNet net{};          // the loaded network (domain of the model)

@@ -71,7 +71,14 @@ __global__ __launch_bounds__(TILE) void k_guess_eval(int64_t n, const double *__
     }
     const double r0sq = fma(x[0], x[0], fma(x[1], x[1], x[2] * x[2]));
     const bool ok = valid && r0sq > 0.0;
-    kep::NetGuess<MODE> gp(net, (int)k, 0);
+    double s_net = __builtin_nan("");
+    if (MODE == 2) {
+        const bool cand = ok && kep::pair_may_qualify(net, t, m, r0sq);
+        if (__any(cand))
+            s_net = kep::net_starter(net, t, cand ? m : 0.0, x[0], x[1], x[2], w[0], w[1], w[2],
+                                     r0sq);
+    }
+    kep::NetGuess<MODE> gp(net, (int)k, 0, s_net);
     const kep::PairFlow f = kep::kepler_flow(ok ? t : 0.0, ok ? m : 0.0, x[0], x[1], x[2], w[0],
                                              w[1], w[2], ok ? r0sq : 1.0, kp, gp);
     if (!valid) return;
@@ -336,6 +343,7 @@ bool domain_ok(const double d[4])
 void set_domain(kep::GuessNet &g, const double d[4])
 {
     g.tau2_lo = d[0] * d[0];
+    g.tau4_lo = g.tau2_lo * g.tau2_lo;
     g.tau2_hi = std::isinf(d[1]) ? HUGE_VAL : d[1] * d[1];
     g.b_lo = d[2];
     g.e2_hi = std::isinf(d[3]) ? HUGE_VAL : d[3] * d[3];
@@ -466,6 +474,7 @@ int sakura_guess_eval(sakura_t *h, int64_t n, const double *tau, const double *m
     if (mode < 0) return fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
     if (mode == 0) { // no model: nothing is in the domain
         net.tau2_lo = HUGE_VAL;
+        net.tau4_lo = HUGE_VAL;
         net.tau2_hi = -1.0;
     }
     SAKURA_HIP(h, hipSetDevice(h->device));

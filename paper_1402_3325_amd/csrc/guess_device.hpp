@@ -49,10 +49,15 @@ struct GuessNet {
     float in_shift[NET_IN], in_scale[NET_IN];
     float out_shift, out_scale;
     double tau2_lo, tau2_hi, b_lo, e2_hi; // domain: tau'^2 range, b' >= b_lo, e'^2 <= e2_hi
+    double tau4_lo;                       // tau_lo^4, for the pre-test of pair_may_qualify
     float *rows;                          // harvest rows (device)
     unsigned long long *row_count;        // rows offered so far (device)
     long long row_cap;
+    int2 *defer_pairs; // [tiles][DEFER_CAP] pairs (i, j) listed by the tile kernel
+    int *defer_count;  // [tiles] entries of each listed tile
+    int *defer_tiles;  // compact list of the tiles with entries
 };
+constexpr int DEFER_CAP = 16; // listed pairs per 64 x 64 tile and step
 
 // Domain test without divisions or square roots: tau'^2 = u^2 mu / r0,
 // b' >= b_lo  <=>  beta r0 >= b_lo mu,  e'^2 <= e_hi^2  <=>  eta^2 <= e_hi^2 mu r0.
@@ -131,39 +136,44 @@ __device__ inline float guess_net_eval(const GuessNet &g, const float f[NET_IN])
     for (int nb = 0; nb < 2; ++nb) {
         asm volatile("" ::: "memory");
         const v4s_t xb = (nb == h) ? own : oth;
-        // layer 1 with the bias as the initial accumulator
-        v16f_t a0, a1;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int row = 8 * (i >> 2) + (i & 3);
-            a0[i] = b1h[row];
-            a1[i] = b1h[32 + row];
-        }
-        a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(w1a, xb, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(w1b, xb, a1, 0, 0, 0);
-        // ReLU, bf16: the B operands of layer 2 (chunk c = hidden rows 16c..16c+15)
+        // layer 1, then bias, ReLU and bf16: the B operands of layer 2
+        // (chunk c = hidden rows 16c..16c+15)
+        const v16f_t zero = {};
         v8bf_t bfrag[4];
+        {
+            const v16f_t a0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(w1a, xb, zero, 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            bfrag[0][j] = (__bf16)fmaxf(a0[j], 0.0f);
-            bfrag[1][j] = (__bf16)fmaxf(a0[8 + j], 0.0f);
-            bfrag[2][j] = (__bf16)fmaxf(a1[j], 0.0f);
-            bfrag[3][j] = (__bf16)fmaxf(a1[8 + j], 0.0f);
+            for (int j = 0; j < 8; ++j) {
+                const int r0 = 8 * (j >> 2) + (j & 3), r1 = 16 + r0;
+                bfrag[0][j] = (__bf16)fmaxf(a0[j] + b1h[r0], 0.0f);
+                bfrag[1][j] = (__bf16)fmaxf(a0[8 + j] + b1h[r1], 0.0f);
+            }
+        }
+        asm volatile("" ::: "memory");
+        {
+            const v16f_t a1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(w1b, xb, zero, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int r0 = 32 + 8 * (j >> 2) + (j & 3), r1 = 16 + r0;
+                bfrag[2][j] = (__bf16)fmaxf(a1[j] + b1h[r0], 0.0f);
+                bfrag[3][j] = (__bf16)fmaxf(a1[8 + j] + b1h[r1], 0.0f);
+            }
         }
         float part = 0.0f;
 #pragma unroll
         for (int mo = 0; mo < 2; ++mo) {
             asm volatile("" ::: "memory");
-            v16f_t c;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) c[i] = b2h[32 * mo + 8 * (i >> 2) + (i & 3)];
+            v16f_t c = zero;
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch)
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(g.w2f[(mo * 4 + ch) * 64 + lane],
                                                             bfrag[ch], c, 0, 0, 0);
+            asm volatile("" ::: "memory");
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                part = fmaf(w3h[32 * mo + 8 * (i >> 2) + (i & 3)], fmaxf(c[i], 0.0f), part);
+            for (int i = 0; i < 16; ++i) {
+                const int row = 32 * mo + 8 * (i >> 2) + (i & 3);
+                part = fmaf(w3h[row], fmaxf(c[i] + b2h[row], 0.0f), part);
+            }
         }
         part += __shfl_xor(part, 32, 64);
         if (nb == h) result = part + g.b3;
@@ -171,11 +181,55 @@ __device__ inline float guess_net_eval(const GuessNet &g, const float f[NET_IN])
     return result;
 }
 
+// Necessary condition for the domain, from the unreduced tau and |x0|^2 only:
+// tau'^2 >= tau_lo^2 with |t| <= |tau| reads tau^4 mu^2 >= tau_lo^4 r0^6.
+SAKURA_HD inline bool pair_may_qualify(const GuessNet &g, double tau, double mu, double r0sq)
+{
+    const double t2 = tau * tau;
+    return mu > 0.0 && t2 * t2 * (mu * mu) >= g.tau4_lo * (r0sq * r0sq * r0sq);
+}
+
+#ifndef SAKURA_HOST_ONLY
+// The network's starter for a pair, or NaN outside the domain: the setup of
+// the root search (period reduction, tau', e', b'), the inputs and the fused
+// evaluation.  Every lane of the wavefront must call it together; a lane
+// without a pair passes mu = 0.  Called ahead of the root search, where little
+// else is live, so the evaluation does not raise the search's register use.
+__device__ inline double net_starter(const GuessNet &g, double tau, double mu, double x0,
+                                     double x1, double x2, double w0, double w1, double w2,
+                                     double r0sq)
+{
+    const bool ok = mu > 0.0 && r0sq > 0.0;
+    const double rs = ok ? r0sq : 1.0;
+    const double r0inv = rsqrt_refined(rs);
+    const double r0 = rs * r0inv;
+    const double eta = fma(x0, w0, fma(x1, w1, x2 * w2));
+    const double vsq = fma(w0, w0, fma(w1, w1, w2 * w2));
+    const double beta = fma(2.0 * mu, r0inv, -vsq);
+    double t = tau;
+    if (beta > 0.0) {
+        const double ib = rsqrt_refined(beta);
+        const double P = 6.283185307179586 * mu * ib * ib * ib;
+        if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
+    }
+    const double u = t * r0inv;
+    const bool dom = ok && guess_domain(g, mu, r0, r0inv, eta, beta, u);
+    float f[NET_IN];
+    guess_inputs(dom ? mu : 1.0, dom ? r0 : 1.0, dom ? r0inv : 1.0, dom ? eta : 0.0,
+                 dom ? beta : 1.0, dom ? t : 1.0, dom ? u : 1.0, f);
+    const float o = guess_net_eval(g, f);
+    return dom ? u * (double)__expf(fmaf(g.out_scale, o, g.out_shift)) : __builtin_nan("");
+}
+#endif
+
 // Starter policies with a loaded network.  MODE 1: plain starter, domain
-// membership recorded; MODE 2: the network's starter for pairs in the domain;
-// MODE 3: plain starter, and every pair in the domain appends a harvest row
-// {8 raw inputs, y = log(s r0 / t) at the converged root, i, j, evaluations}
-// (the last three as int32 bits).
+// membership recorded; MODE 2: the network's starter (s_net, computed ahead
+// by net_starter) for pairs in the domain; MODE 3: plain starter, and every
+// pair in the domain appends a harvest row {8 raw inputs, y = log(s r0 / t) at
+// the converged root, i, j, evaluations} (the last three as int32 bits);
+// MODE 4: pairs in the domain are skipped and listed for k_deferred (up to
+// the wave's remaining list capacity, *room; beyond it they are solved here
+// with the plain starter).
 template <int MODE>
 struct NetGuess {
     static constexpr bool active = true;
@@ -183,29 +237,43 @@ struct NetGuess {
     int pi, pj;          // particle indices (harvest rows)
     bool in_dom = false; // the pair lies in the network's domain
     bool used = false;   // the network's starter replaced the plain one
+    bool deferred = false; // MODE 4: skipped here, listed for the deferred kernel
+    int slot = 0;        // MODE 4: position in the wave's list
     double s_start = 0.0, s_root = 0.0;
+    double s_net;        // MODE 2: the network's starter from net_starter (NaN: none)
+    int *room;           // MODE 4: list slots left (wave-uniform)
 
-    __device__ NetGuess(const GuessNet &net, int i, int j) : g(net), pi(i), pj(j) {}
+    __device__ NetGuess(const GuessNet &net, int i, int j, double snet = __builtin_nan(""),
+                        int *room_left = nullptr)
+        : g(net), pi(i), pj(j), s_net(snet), room(room_left) {}
 
-    __device__ bool start(double t, double mu, double r0, double r0inv, double eta,
-                          double beta, double u, double lo, double hi, double &s)
+    __device__ int start(double t, double mu, double r0, double r0inv, double eta,
+                         double beta, double u, double lo, double hi, double &s)
     {
         in_dom = guess_domain(g, mu, r0, r0inv, eta, beta, u);
         s_start = s;
-        if (MODE != 2 || !__any(in_dom)) return false;
-        float f[NET_IN];
-        // lanes outside the domain evaluate a harmless problem
-        guess_inputs(in_dom ? mu : 1.0, in_dom ? r0 : 1.0, in_dom ? r0inv : 1.0,
-                     in_dom ? eta : 0.0, in_dom ? beta : 1.0, in_dom ? t : 1.0,
-                     in_dom ? u : 1.0, f);
-        const float o = guess_net_eval(g, f);
-        if (!in_dom) return false;
-        const double sl = u * (double)__expf(fmaf(g.out_scale, o, g.out_shift));
-        if (!(sl > lo && sl < hi)) return false; // also rejects NaN
-        s = sl;
-        s_start = sl;
+        if (MODE == 4) {
+            const unsigned long long mask = __ballot(in_dom);
+            if (!mask) return START_PLAIN;
+            const int lane = threadIdx.x & 63;
+            const unsigned long long below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+            // (__popcll is unsigned: keep the arithmetic in int)
+            const int rank = (int)__popcll(below);
+            const int total = (int)__popcll(mask);
+            const int avail = *room;
+            *room = avail > total ? avail - total : 0;
+            if (in_dom && rank < avail) {
+                deferred = true;
+                slot = rank;
+                return START_SKIP;
+            }
+            return START_PLAIN;
+        }
+        if (MODE != 2 || !in_dom || !(s_net > lo && s_net < hi)) return START_PLAIN; // also NaN
+        s = s_net;
+        s_start = s_net;
         used = true;
-        return true;
+        return START_REPLACED;
     }
 
     __device__ void done(double s, double t, double mu, double r0, double r0inv, double eta,

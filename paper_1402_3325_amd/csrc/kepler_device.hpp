@@ -251,11 +251,14 @@ SAKURA_HD inline void analytic_start(double t, double u, double r0, double r0inv
 
 // A starter policy sees every pair between the plain starter and the root
 // search (all lanes of the wavefront together) and again after the search.
-// NoGuess keeps the plain starter.
+// start() returns START_PLAIN (keep the plain starter), START_REPLACED (it
+// replaced s) or START_SKIP (the pair is solved elsewhere: the flow returns
+// zero coefficients at once).  NoGuess keeps the plain starter.
+enum { START_PLAIN = 0, START_REPLACED = 1, START_SKIP = 2 };
 struct NoGuess {
     static constexpr bool active = false;
-    SAKURA_HD bool start(double, double, double, double, double, double, double, double,
-                         double, double &) { return false; }
+    SAKURA_HD int start(double, double, double, double, double, double, double, double,
+                        double, double &) { return START_PLAIN; }
     SAKURA_HD void done(double, double, double, double, double, double, double, int) {}
 };
 
@@ -306,7 +309,18 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
     double s, lo, hi;
     analytic_start(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, s, lo, hi);
     bool replaced = false;
-    if (Guess::active) replaced = guess.start(t, mu, r0, r0inv, eta, beta, u, lo, hi, s);
+    if (Guess::active) {
+        const int how = guess.start(t, mu, r0, r0inv, eta, beta, u, lo, hi, s);
+        if (how == START_SKIP) {
+            PairFlow z;
+            z.fm1 = z.gmt = z.fdot = z.gdm1 = 0.0;
+            z.iters = 0;
+            z.converged = true;
+            z.safeguarded = z.restarted = false;
+            return z;
+        }
+        replaced = how == START_REPLACED;
+    }
 
     KepIter st{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
     int it = 0;

@@ -11,6 +11,8 @@
 // caller's [n][3] arrays and the internal layout once per call.
 #include "common.hpp"
 
+#include <algorithm>
+
 __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
 {
     const int t = threadIdx.x; // NSLOT threads
@@ -34,6 +36,8 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
         c->dom_iters = 0;
         c->learned = 0;
         c->restarts = 0;
+        c->defer_ntiles = 0;
+        c->defer_next = 0;
     }
     if (t < 32) c->hist[t] = 0;
 }
@@ -120,6 +124,22 @@ __device__ inline double from_next_lane(double x)
     return __hiloint2double(hi, lo);
 }
 
+// Blocks (I, J), I <= J, of tile t: off-diagonal tiles first (twice the work
+// of a diagonal one), column by column, then the diagonal.
+__device__ inline void tile_blocks(int t, int nb, int &I, int &J)
+{
+    const int noff = nb * (nb - 1) / 2;
+    if (t < noff) {
+        int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+        while (j * (j - 1) / 2 > t) --j;
+        while ((j + 1) * j / 2 <= t) ++j;
+        J = j;
+        I = t - j * (j - 1) / 2;
+    } else {
+        I = J = t - noff;
+    }
+}
+
 // All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
 //
 // Lane l holds particle i = 64 I + l; block J sits in LDS (read only).  In
@@ -131,7 +151,8 @@ __device__ inline double from_next_lane(double x)
 // s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
 // Partial sums go to part[I][J] (i side) and part[J][I] (j side).
 // MODE selects the starter: 0 plain; with a loaded network 1 plain with
-// domain statistics, 2 the network's starter, 3 plain with harvest rows.
+// domain statistics, 3 plain with harvest rows, 4 pairs in the network's
+// domain listed for k_deferred (which starts them from the network).
 template <bool HIST, int MODE>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
@@ -141,18 +162,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                                                 const kep::GuessNet net)
 {
     if (cnt->status) return; // an earlier failure: the call will report it
-    const int t = blockIdx.x;
-    const int noff = nb * (nb - 1) / 2;
     int I, J;
-    if (t < noff) { // off-diagonal tiles first (twice the work of a diagonal one)
-        int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
-        while (j * (j - 1) / 2 > t) --j;
-        while ((j + 1) * j / 2 <= t) ++j;
-        J = j;
-        I = t - j * (j - 1) / 2;
-    } else {
-        I = J = t - noff;
-    }
+    tile_blocks(blockIdx.x, nb, I, J);
     const bool diag = (I == J);
     const int lane = threadIdx.x;
 
@@ -193,6 +204,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     unsigned long long n_solve = 0, n_fb = 0; // per wave (ballot counts)
     GuessCount gc;                            // per wave
     unsigned dom_it = 0;                      // per lane
+    int room = kep::DEFER_CAP;                // MODE 4: list slots left
     bool any_noconv = false, any_collide = false;
     __syncthreads();
 
@@ -213,23 +225,25 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         double x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
-        const bool live = act && !collide;
+        bool live = act && !collide;
         // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
         kep::PairFlow f;
         if constexpr (MODE == 0) {
             f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
                                  w2, live ? r0sq : 1.0, kp);
         } else {
-            kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
+            const int listed = kep::DEFER_CAP - room;
+            kep::NetGuess<MODE> gp(net, ig, J * TILE + q, __builtin_nan(""), &room);
             f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
                                  w2, live ? r0sq : 1.0, kp, gp);
+            if (MODE == 4 && gp.deferred) {
+                net.defer_pairs[(size_t)blockIdx.x * kep::DEFER_CAP + listed + gp.slot] =
+                    make_int2(ig, J * TILE + q);
+                live = false; // solved, and counted, by k_deferred
+            }
             const bool dom = live && gp.in_dom;
             gc.dom += __popcll(__ballot(dom));
             dom_it += dom ? (unsigned)f.iters : 0u;
-            if (MODE == 2) {
-                gc.learned += __popcll(__ballot(live && gp.used));
-                gc.restarts += __popcll(__ballot(live && f.restarted));
-            }
         }
         // the same relative state again, from LDS (bitwise equal to the above)
         asm volatile("" ::: "memory");
@@ -290,8 +304,111 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
         if (MODE != 0) slot_add_guess(slots, blockIdx.x, gc);
         if (flags) record_error(cnt, flags, step);
+        if (MODE == 4 && room < kep::DEFER_CAP) {
+            net.defer_count[blockIdx.x] = kep::DEFER_CAP - room;
+            net.defer_tiles[atomicAdd(&cnt->defer_ntiles, 1u)] = blockIdx.x;
+        }
     }
     if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
+}
+
+// The pairs of the network's domain that k_pairs listed (MODE 4): up to 64
+// of one tile per wavefront, started from the network's value (fused MFMA
+// evaluation) and solved with the same root search; their weighted increments
+// are added to the tile's partial sums in list order by one lane, so the
+// result does not depend on the order in which tiles are taken.  Persistent:
+// every wave leaves once the list is exhausted.
+__global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, double G,
+                                                   const double *__restrict__ S,
+                                                   double *__restrict__ part, DevCounters *cnt,
+                                                   SlotStats *slots, kep::KeplerParams kp,
+                                                   long long step, const kep::GuessNet net)
+{
+    if (cnt->status) return;
+    const int lane = threadIdx.x;
+    const double *M = S;
+    const double *V = S + 4 * (size_t)np;
+    const double *XH = S + 7 * (size_t)np;
+    const double h = 0.5 * tau;
+    unsigned long long n_solve = 0, n_fb = 0;
+    unsigned it_sum = 0, it_max = 0;
+    GuessCount gc;
+    bool any_noconv = false;
+    const unsigned ntl = cnt->defer_ntiles;
+    for (;;) {
+        unsigned item = 0;
+        if (lane == 0) item = atomicAdd(&cnt->defer_next, 1u);
+        item = __shfl(item, 0, 64);
+        if (item >= ntl) break;
+        const int tile = net.defer_tiles[item];
+        const int count = net.defer_count[tile];
+        int I, J;
+        tile_blocks(tile, nb, I, J);
+        const bool has = lane < count;
+        int i = I * TILE, j = J * TILE + 1;
+        if (has) {
+            const int2 p = net.defer_pairs[(size_t)tile * kep::DEFER_CAP + lane];
+            i = p.x;
+            j = p.y;
+        }
+        // the relative state exactly as k_pairs forms it
+        const double mi = M[i], mj = M[j];
+        const double msum = mi + mj;
+        const double w0 = V[i] - V[j], w1 = V[np + i] - V[np + j],
+                     w2 = V[2 * (size_t)np + i] - V[2 * (size_t)np + j];
+        const double x0 = fma(-h, w0, XH[i] - XH[j]);
+        const double x1 = fma(-h, w1, XH[np + i] - XH[np + j]);
+        const double x2 = fma(-h, w2, XH[2 * (size_t)np + i] - XH[2 * (size_t)np + j]);
+        const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+        const double mu = has ? G * msum : 0.0;
+        const double s_net = kep::net_starter(net, tau, mu, x0, x1, x2, w0, w1, w2, r0sq);
+        kep::NetGuess<2> gp(net, i, j, s_net);
+        const kep::PairFlow f = kep::kepler_flow(has ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2,
+                                                 has ? r0sq : 1.0, kp, gp);
+        const double a = fma(-h, f.fdot, f.fm1);
+        const double b = fma(-h, f.gdm1, f.gmt);
+        const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
+                             fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
+                             fma(f.fdot, x2, f.gdm1 * w2)};
+        const double inv = has ? kep::rcp_refined(msum) : 0.0;
+        const double wgt_i = mj * inv, wgt_j = mi * inv;
+        double ci[6], cj[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            ci[c] = wgt_i * d[c];
+            cj[c] = -wgt_j * d[c];
+        }
+        // list order, one lane: part[I][J] holds the i side, part[J][I] the j side
+        double *pi = part + ((size_t)I * nb + J) * 6 * TILE;
+        double *pj = part + ((size_t)J * nb + I) * 6 * TILE;
+        for (int k = 0; k < count; ++k) {
+            const int ik = __shfl(i, k, 64) - I * TILE, jk = __shfl(j, k, 64) - J * TILE;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double vi = __shfl(ci[c], k, 64), vj = __shfl(cj[c], k, 64);
+                if (lane == 0) {
+                    pi[c * TILE + ik] += vi;
+                    pj[c * TILE + jk] += vj;
+                }
+            }
+        }
+        n_solve += __popcll(__ballot(has));
+        n_fb += __popcll(__ballot(has && f.safeguarded));
+        it_sum += has ? f.iters : 0;
+        it_max = max(it_max, has ? (unsigned)f.iters : 0u);
+        gc.dom += __popcll(__ballot(has && gp.in_dom));
+        gc.dom_iters += wave_sum(has && gp.in_dom ? (unsigned)f.iters : 0u);
+        gc.learned += __popcll(__ballot(has && gp.used));
+        gc.restarts += __popcll(__ballot(has && f.restarted));
+        any_noconv = any_noconv || __ballot(has && !f.converged) != 0;
+    }
+    it_sum = wave_sum(it_sum);
+    it_max = wave_max(it_max);
+    if (lane == 0) {
+        slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+        slot_add_guess(slots, blockIdx.x, gc);
+        if (any_noconv) record_error(cnt, ST_NOCONV, step);
+    }
 }
 
 // Deterministic compensated reduction of the partial sums of one block K
@@ -304,6 +421,10 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, doubl
 {
     const int K = blockIdx.x;
     const int c = threadIdx.x / TILE, lane = threadIdx.x % TILE;
+    if (K == 0 && threadIdx.x == 0) { // the deferred-pair list of this step is consumed
+        cnt->defer_ntiles = 0;
+        cnt->defer_next = 0;
+    }
     __shared__ double dsum[6][TILE];
     const double *p = part + ((size_t)K * nb * 6 + c) * TILE + lane;
     const size_t stride = 6 * TILE;
@@ -475,8 +596,10 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
     case 1:
         k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
         break;
-    case 2:
-        k_pairs<HIST, 2><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+    case 2: // the network's starter: pairs of its domain go through k_deferred
+        k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, G, S, part, cnt, slots, kp,
+                                                          step, net);
         break;
     case 3:
         k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
@@ -553,6 +676,8 @@ void sakura_destroy(sakura_t *h)
     if (h->batch_offsets) (void)hipFree(h->batch_offsets);
     if (h->tune_rv) (void)hipFree(h->tune_rv);
     if (h->net_buf) (void)hipFree(h->net_buf);
+    if (h->defer_pairs) (void)hipFree(h->defer_pairs);
+    if (h->defer_idx) (void)hipFree(h->defer_idx);
     if (h->row_count) (void)hipFree(h->row_count);
     if (h->mlp_buf) (void)hipFree(h->mlp_buf);
     if (h->mlp_part) (void)hipFree(h->mlp_part);
@@ -596,6 +721,14 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     kep::GuessNet net{};
     const int mode = sk::guess_mode(h, &net);
     if (mode < 0) return sk::fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
+    if (mode == 2) { // lists of deferred pairs
+        if ((rc = sk::grow(h, &h->defer_pairs, &h->cap_defer, (int64_t)ntiles * kep::DEFER_CAP)))
+            return rc;
+        if ((rc = sk::grow(h, &h->defer_idx, &h->cap_defer_idx, 2 * (int64_t)ntiles))) return rc;
+        net.defer_pairs = h->defer_pairs;
+        net.defer_count = h->defer_idx;
+        net.defer_tiles = h->defer_idx + ntiles;
+    }
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
     sk::k_clear<<<1, sk::NSLOT, 0, st>>>(h->cnt, h->slots);

@@ -364,3 +364,63 @@ def test_training_and_what_the_network_changes(torch, lib):
     assert er <= TOL and ev <= TOL, (er, ev)
     assert sl["guess_restarts"] == 0
     assert learned < plain
+
+
+def test_learned_deferral_overflow_matches_oracle(torch, lib, oracle):
+    """A compact group where most of the 64 x 64 tile's pairs lie in the domain:
+    the tile lists 16 of them per step for the deferred kernel and solves the
+    rest in place with the plain starter; the step still matches the oracle."""
+    from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
+    rng = np.random.default_rng(41)
+    n = 100
+    m = np.full(n, 1.0 / n)
+    r = rng.normal(size=(n, 3)) * 0.05
+    v = rng.normal(size=(n, 3)) * 0.3
+    r -= (m[:, None] * r).sum(0) / m.sum()
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    tau = 0.02
+    mu, X, W, T = kepler_problems(2000, 25)
+    F, Y, D = oracle_samples(oracle, mu, X, W, T)
+    lib.set_guess_model(make_model(np.random.default_rng(6), F, D))
+    try:
+        lib.set_guess(GUESS_LEARNED)
+        mt, rt, vt = _dev(torch, m, r, v)
+        st = lib.evolve(mt, rt, vt, tau, 1, stats=True)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_guess(GUESS_ANALYTIC)
+        lib.set_guess_model(None)
+    rr, vr = oracle.step(m, r.copy(), v.copy(), tau)
+    er, ev = step_error(rt.cpu().numpy(), vt.cpu().numpy(), rr, vr, r, v)
+    assert er <= TOL and ev <= TOL, (er, ev)
+    ntiles = 3  # two blocks of 64: tiles (0,0), (0,1), (1,1)
+    assert st["guess_domain_pairs"] > 16 * ntiles
+    assert 0 < st["guess_learned"] <= 16 * ntiles
+    assert st["pair_solves"] == n * (n - 1) // 2
+
+
+def test_learned_batched_matches_oracle(torch, lib, oracle):
+    from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
+    off, m, r, v, tau = workloads.ensemble(n_sys=48, seed=workloads.SEED_BASE + 105)
+    tau = tau * 8  # longer steps: more pairs in the domain
+    mu, X, W, T = kepler_problems(2000, 26)
+    F, Y, D = oracle_samples(oracle, mu, X, W, T)
+    dom = [0.05, 64.0, -1.0, 3.0]
+    model = make_model(np.random.default_rng(8), F, D)
+    model["domain"] = dom
+    lib.set_guess_model(model)
+    try:
+        lib.set_guess(GUESS_LEARNED)
+        mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+        st = lib.batch_evolve(off, mt, rt, vt, dtt, 1, stats=True)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_guess(GUESS_ANALYTIC)
+        lib.set_guess_model(None)
+    assert st["guess_learned"] > 0
+    R, V = rt.cpu().numpy(), vt.cpu().numpy()
+    for s in range(len(off) - 1):
+        a, b = off[s], off[s + 1]
+        rr, vr = oracle.step(m[a:b], r[a:b].copy(), v[a:b].copy(), tau[s])
+        er, ev = step_error(R[a:b], V[a:b], rr, vr, r[a:b], v[a:b])
+        assert er <= TOL and ev <= TOL, (s, er, ev)
