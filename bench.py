@@ -33,8 +33,12 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 FLOPS_FIXED = 19 + 47 + 28 + 19 + 57
 FLOPS_PER_ITER = 72 + 18
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
+                  "paper_1402_3325_amd/csrc/guess_device.hpp",
                   "paper_1402_3325_amd/csrc/common.hpp",
                   "paper_1402_3325_amd/csrc/sakura.hip"]
+# domain of the learned starter: tau' in [0.25, 64], b' >= -1, |e'| <= 3 (pairs the
+# plain starter needs three or more Kepler evaluations for)
+GUESS_DOMAIN = [0.25, 64.0, -1.0, 3.0]
 TRAFFIC_FILE = "profiles/k_pairs_cluster16384.traffic.json"
 
 
@@ -119,6 +123,90 @@ def batched(lib, torch, steps=256):
                               "tol": 1e-12}}
 
 
+def learned(torch, m, r, v, tau, steps, warmup, plain_value, harvest_steps):
+    """The learned Kepler starter on the same workload.  Rows are harvested
+    with the plain starter from an independent cluster (seed offset 100),
+    the network is trained by the library's own kernels, then the timed run
+    of the main workload is repeated with the network's starter.  Also
+    reports the Kepler evaluations of the pairs in the network's domain with
+    and without it, and the batched ensemble with the network."""
+    from paper_1402_3325_amd import workloads
+    from paper_1402_3325_amd.sakura import Sakura, GUESS_ANALYTIC, GUESS_LEARNED
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    h = Sakura(0)
+    m2, r2, v2, tau2 = workloads.cluster(rng=workloads.rng_for(2, 100))
+    cap = 4_000_000
+    rows = torch.zeros((cap, 12), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    h.harvest_begin(rows, GUESS_DOMAIN)
+    h.evolve(dev(m2), dev(r2), dev(v2), tau2, harvest_steps)
+    offered = h.harvest_end()
+    t_harvest = time.perf_counter() - t0
+    nrows = min(offered, cap)
+    t0 = time.perf_counter()
+    model, hist = h.mlp_fit(rows[:nrows], GUESS_DOMAIN, epochs=20, batch=4096, seed=1)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    del rows
+    h.close()
+
+    res = {}
+    for mode in (GUESS_ANALYTIC, GUESS_LEARNED):
+        hh = Sakura(0, guess=mode)
+        hh.set_guess_model(model)  # plain starter + model: domain statistics only
+        mt, rt, vt = dev(m), dev(r), dev(v)
+        if warmup:
+            hh.evolve(mt, rt, vt, tau, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = hh.evolve(mt, rt, vt, tau, steps, stats=True)
+        torch.cuda.synchronize()
+        res[mode] = (st, time.perf_counter() - t0, hh)
+    st_p, _, hp = res[GUESS_ANALYTIC]
+    st_l, wall_l, hl = res[GUESS_LEARNED]
+    n = len(m)
+    pairs = n * (n - 1) // 2
+    value = pairs * steps / wall_l
+    rows_s = np.unique(np.concatenate([[0], np.random.default_rng(12).choice(n, 63, replace=False)]))
+    er, ev = parity_sample(hl, torch, m, r, v, tau, rows_s)
+    out = {
+        "value": value, "unit": "pair-solves/s", "vs_plain": value / plain_value,
+        "ms_per_step": wall_l * 1e3 / steps,
+        "pair_kernel_ms": st_l["pair_kernel_ms"] / max(st_l["pair_launches"], 1),
+        "domain": GUESS_DOMAIN,
+        "domain_pairs_per_step": st_l["guess_domain_pairs"] / steps,
+        "domain_mean_iters_plain": st_p["guess_domain_iters"] / max(st_p["guess_domain_pairs"], 1),
+        "domain_mean_iters_learned": st_l["guess_domain_iters"] / max(st_l["guess_domain_pairs"], 1),
+        "max_iters_plain": st_p["iters_max"], "max_iters_learned": st_l["iters_max"],
+        "mean_kepler_iters": st_l["iters_total"] / max(st_l["pair_solves"], 1),
+        "network_starts": st_l["guess_learned"], "restarts": st_l["guess_restarts"],
+        "training": {"harvest": f"{harvest_steps} steps of an independent N=16384 cluster "
+                                f"(seed offset 100), plain starter",
+                     "rows": int(nrows), "harvest_s": t_harvest, "fit_s": t_fit,
+                     "epochs": 20, "val_mse_scaled": hist[-1]},
+        "err_vs_oracle": {"err_r": er, "err_v": ev, "rows": int(len(rows_s)), "tol": 1e-12},
+    }
+    hp.close()
+    # the batched ensemble with the same network (few of its pairs reach the domain)
+    off, mb, rb, vb, taub = workloads.ensemble()
+    sizes = np.diff(off)
+    bp = int(np.sum(sizes * (sizes - 1) // 2))
+    mt, rt, vt, dtt = dev(mb), dev(rb), dev(vb), dev(taub)
+    hl.autotune_batch(off, mt, rt, vt, dtt, probe_steps=8)
+    hl.batch_evolve(off, mt, rt, vt, dtt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb = hl.batch_evolve(off, mt, rt, vt, dtt, 256, stats=True)
+    torch.cuda.synchronize()
+    wb = time.perf_counter() - t0
+    out["batched"] = {"value": bp * 256 / wb, "unit": "pair-solves/s",
+                      "domain_pairs": sb["guess_domain_pairs"],
+                      "domain_mean_iters": sb["guess_domain_iters"] / max(sb["guess_domain_pairs"], 1),
+                      "network_starts": sb["guess_learned"]}
+    hl.close()
+    return out
+
+
 def cpu_baseline(m, r, v, tau, budget_s=15.0):
     """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
     a bounded sample: rows of one step of the same workload."""
@@ -149,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--harvest-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (x4), to scale "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -227,6 +317,9 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched(lib, torch)
+    if not args.no_learned:
+        out["learned"] = learned(torch, m, r, v, tau, args.steps, args.warmup, out["value"],
+                                 args.harvest_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, r, v, tau)
     print(json.dumps(out), flush=True)

@@ -312,12 +312,12 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
 }
 
-// The pairs of the network's domain that k_pairs listed (MODE 4): up to 64
-// of one tile per wavefront, started from the network's value (fused MFMA
+// The pairs of the network's domain that k_pairs listed (MODE 4): the list of
+// one tile per wavefront, started from the network's value (fused MFMA
 // evaluation) and solved with the same root search; their weighted increments
-// are added to the tile's partial sums in list order by one lane, so the
-// result does not depend on the order in which tiles are taken.  Persistent:
-// every wave leaves once the list is exhausted.
+// are added to the tile's partial sums in list order, one lane per component,
+// so the result does not depend on the order in which tiles are taken.
+// Persistent: every wave leaves once the list is exhausted.
 __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, double G,
                                                    const double *__restrict__ S,
                                                    double *__restrict__ part, DevCounters *cnt,
@@ -325,6 +325,8 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
                                                    long long step, const kep::GuessNet net)
 {
     if (cnt->status) return;
+    __shared__ double sc[TILE][12]; // weighted increments of the listed pairs
+    __shared__ int sidx[TILE][2];   // their slots in blocks I and J
     const int lane = threadIdx.x;
     const double *M = S;
     const double *V = S + 4 * (size_t)np;
@@ -372,24 +374,23 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
                              fma(f.fdot, x2, f.gdm1 * w2)};
         const double inv = has ? kep::rcp_refined(msum) : 0.0;
         const double wgt_i = mj * inv, wgt_j = mi * inv;
-        double ci[6], cj[6];
+        __syncthreads(); // the previous item's readers of sc are done
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            ci[c] = wgt_i * d[c];
-            cj[c] = -wgt_j * d[c];
+            sc[lane][c] = wgt_i * d[c];
+            sc[lane][6 + c] = -wgt_j * d[c];
         }
-        // list order, one lane: part[I][J] holds the i side, part[J][I] the j side
-        double *pi = part + ((size_t)I * nb + J) * 6 * TILE;
-        double *pj = part + ((size_t)J * nb + I) * 6 * TILE;
-        for (int k = 0; k < count; ++k) {
-            const int ik = __shfl(i, k, 64) - I * TILE, jk = __shfl(j, k, 64) - J * TILE;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const double vi = __shfl(ci[c], k, 64), vj = __shfl(cj[c], k, 64);
-                if (lane == 0) {
-                    pi[c * TILE + ik] += vi;
-                    pj[c * TILE + jk] += vj;
-                }
+        sidx[lane][0] = i - I * TILE;
+        sidx[lane][1] = j - J * TILE;
+        __syncthreads();
+        // list order: lane c < 6 adds component c of every listed pair, i side to
+        // part[I][J], j side to part[J][I] (no two lanes touch one address)
+        if (lane < 6) {
+            double *pi = part + (((size_t)I * nb + J) * 6 + lane) * TILE;
+            double *pj = part + (((size_t)J * nb + I) * 6 + lane) * TILE;
+            for (int k = 0; k < count; ++k) {
+                pi[sidx[k][0]] += sc[k][lane];
+                pj[sidx[k][1]] += sc[k][6 + lane];
             }
         }
         n_solve += __popcll(__ballot(has));
