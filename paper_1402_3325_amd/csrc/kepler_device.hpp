@@ -136,15 +136,31 @@ struct KepIter {
 // Returns 1 when st.s is the root (G-functions and r left at st.s), 2 when
 // st.s - ds is (G-functions carried there by their Taylor series), 0 when the
 // search goes on from the new st.s.
-template <bool SMALL_Z>
+//
+// TIER says what every lane of the wavefront has in common: 0 nothing;
+// 1 |z| <= 2^-10 (four-term Stumpff series); 2 |z| <= 2^-14, where three terms
+// of each series leave a truncation below 2^-56, the Laguerre step is taken in
+// its Halley form F r / (r^2 - F F''/2) while |F F''| <= 2^-22 r^2 (the two
+// agree to a relative q^2/10, q = 5 F F'' / 4 r^2, i.e. below 2^-42), and an
+// accepted step moves the G-functions by their Taylor series to first order
+// when |ds| <= 2^-28 |s| on every accepting lane, to second order when
+// |ds| <= 2^-18 |s| (the dropped terms are then below 3 (ds/s)^2 resp.
+// (ds/s)^3, i.e. below 2^-54 of each function), else to third order.
+template <int TIER>
 SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double zeta,
                                     double r0, double t, double tol)
 {
     const double s = st.s;
     const double z = beta * s * s;
     double c2, c3;
-    if (SMALL_Z) stumpff23_small(z, c2, c3);
-    else stumpff23(z, c2, c3);
+    if (TIER == 2) {
+        c2 = fma(fma(z, 1.0 / 720.0, -1.0 / 24.0), z, 0.5);
+        c3 = fma(fma(z, 1.0 / 5040.0, -1.0 / 120.0), z, 1.0 / 6.0);
+    } else if (TIER == 1) {
+        stumpff23_small(z, c2, c3);
+    } else {
+        stumpff23(z, c2, c3);
+    }
     const double s2 = s * s;
     const double G1 = s * fma(-z, c3, 1.0);
     const double G2 = s2 * c2;
@@ -155,8 +171,14 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     const double Fpp = fma(eta, G0, zeta * G1);
     if (F < 0.0) st.lo = s;
     else st.hi = s;
-    const double disc = fma(16.0 * r, r, -20.0 * F * Fpp);
-    const double ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
+    const double FFpp = F * Fpp;
+    double ds;
+    if (TIER == 2 && fabs(FFpp) <= 0x1p-22 * (r * r)) {
+        ds = F * r * rcp_step(fma(-0.5, FFpp, r * r));
+    } else {
+        const double disc = fma(16.0 * r, r, -20.0 * FFpp);
+        ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
+    }
     const double ads = fabs(ds), as = fabs(s);
     // Converged at s: the correction is below tol |s|, or it sits at the
     // rounding floor of F (tiny and no longer shrinking).
@@ -181,11 +203,23 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     const double err_r2 = fma(aFpp * ads2, r, ads2 * ads * fma(fabs(Fppp), r, aFpp * aFpp));
     if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * r * r && sn >= st.lo &&
         sn <= st.hi) {
-        const double d = -ds, d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
-        const double mbG1 = -beta * G1, mbG0 = -beta * G0;
-        st.G3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
-        st.G2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
-        st.G1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
+        const double d = -ds;
+        if (TIER == 2 && SAKURA_WAVE_ALL(ads <= 0x1p-28 * asn)) {
+            st.G3 = fma(d, G2, G3);
+            st.G2 = fma(d, G1, G2);
+            st.G1 = fma(d, G0, G1);
+        } else if (TIER == 2 && SAKURA_WAVE_ALL(ads <= 0x1p-18 * asn)) {
+            const double d2 = 0.5 * d * d;
+            st.G3 = fma(d2, G1, fma(d, G2, G3));
+            st.G2 = fma(d2, G0, fma(d, G1, G2));
+            st.G1 = fma(d2, -beta * G1, fma(d, G0, G1));
+        } else {
+            const double d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
+            const double mbG1 = -beta * G1, mbG0 = -beta * G0;
+            st.G3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
+            st.G2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
+            st.G1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
+        }
         st.r = fma(eta, st.G1, fma(zeta, st.G2, r0));
         st.s = sn;
         return 2;
@@ -263,18 +297,23 @@ struct NoGuess {
 };
 
 // Root search from st until convergence or kp.max_iter evaluations; the first
-// evaluation uses the short Stumpff series when every lane of the wavefront
-// qualifies (almost every pair of a star cluster converges there).
+// evaluation takes the cheapest tier every lane of the wavefront qualifies for
+// (almost every pair of a star cluster converges there, in tier 2).
 SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double zeta, double r0,
                                    double t, const KeplerParams &kp, int &it)
 {
-    const bool small_z = SAKURA_WAVE_ALL(fabs(beta * st.s * st.s) <= 0x1p-10);
-    int res = small_z ? kepler_iterate<true>(st, beta, eta, zeta, r0, t, kp.tol)
-                      : kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+    const double z0 = fabs(beta * st.s * st.s);
+    int res;
+    if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
+        res = kepler_iterate<2>(st, beta, eta, zeta, r0, t, kp.tol);
+    else if (SAKURA_WAVE_ALL(z0 <= 0x1p-10))
+        res = kepler_iterate<1>(st, beta, eta, zeta, r0, t, kp.tol);
+    else
+        res = kepler_iterate<0>(st, beta, eta, zeta, r0, t, kp.tol);
     it = 1;
     while (res == 0 && it < kp.max_iter) {
         ++it;
-        res = kepler_iterate<false>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_iterate<0>(st, beta, eta, zeta, r0, t, kp.tol);
     }
     return res;
 }

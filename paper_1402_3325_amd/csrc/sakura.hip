@@ -211,15 +211,18 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
     for (int s = s0; s < s1; ++s) {
         const int q = (lane + s) & (TILE - 1);
-        // Particle data are read from LDS at every use (compiler-only fence:
-        // keeps them out of registers across the Kepler solve).
-        asm volatile("" ::: "memory");
+        // With a starter policy the particle data are read from LDS at every
+        // use and the relative state is formed again after the solve
+        // (compiler-only fences): that policy's extra live state would
+        // otherwise push the loop past 128 VGPRs.  The plain loop keeps it.
+        if (MODE != 0) asm volatile("" ::: "memory");
         const double mi = si[6][lane], mj = sj[6][q];
         const double msum = mi + mj;
         const bool act = valid_i && (q < nj) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         // relative state and the pair back-drift of eq. (17) by tau/2
-        double w0 = si[3][lane] - sj[3][q], w1 = si[4][lane] - sj[4][q], w2 = si[5][lane] - sj[5][q];
+        double w0 = si[3][lane] - sj[3][q], w1 = si[4][lane] - sj[4][q],
+               w2 = si[5][lane] - sj[5][q];
         double x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
         double x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
         double x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
@@ -245,15 +248,16 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             gc.dom += __popcll(__ballot(dom));
             dom_it += dom ? (unsigned)f.iters : 0u;
         }
-        // the same relative state again, from LDS (bitwise equal to the above)
-        asm volatile("" ::: "memory");
-        w0 = si[3][lane] - sj[3][q];
-        w1 = si[4][lane] - sj[4][q];
-        w2 = si[5][lane] - sj[5][q];
-        x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
-        x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
-        x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
 
+        if (MODE != 0) { // the same relative state again, bitwise
+            asm volatile("" ::: "memory");
+            w0 = si[3][lane] - sj[3][q];
+            w1 = si[4][lane] - sj[4][q];
+            w2 = si[5][lane] - sj[5][q];
+            x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
+            x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
+            x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
+        }
         // increments of eq. (26) minus the starting relative state
         const double a = fma(-h, f.fdot, f.fm1);
         const double b = fma(-h, f.gdm1, f.gmt);
