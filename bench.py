@@ -26,12 +26,14 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
 # Algorithmic FP64 operations per pair solve, counted in the kernel source
 # (add/sub/mul and the hardware reciprocal / reciprocal-square-root estimates
-# = 1, fma = 2): pair set-up and back-drift 19, Kepler set-up and starter 47,
-# Taylor shift of the G-functions 28, Lagrange coefficients 19, increments,
-# weights and the two-sided sums 57; each evaluation of the Kepler equation
-# with its Laguerre step 72 plus the convergence estimate 18.
-FLOPS_FIXED = 19 + 47 + 28 + 19 + 57
-FLOPS_PER_ITER = 72 + 18
+# = 1, fma = 2) along the path almost every pair takes (one evaluation of the
+# Kepler equation in the cheapest tier, accepted with a first-order shift of
+# the G-functions): pair set-up and back-drift 19, Kepler set-up and starter
+# 47, the evaluation with its Halley step, convergence estimate and shift 78,
+# Lagrange coefficients 19, increments, weights and the two-sided sums 57;
+# every further evaluation (Laguerre step, general Stumpff series) 90.
+FLOPS_FIRST = 19 + 47 + 78 + 19 + 57
+FLOPS_PER_EXTRA_ITER = 90
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
                   "paper_1402_3325_amd/csrc/common.hpp",
@@ -63,7 +65,7 @@ def measured_traffic():
 
 
 def flops_per_pair(mean_iters):
-    return FLOPS_FIXED + FLOPS_PER_ITER * mean_iters
+    return FLOPS_FIRST + FLOPS_PER_EXTRA_ITER * max(mean_iters - 1.0, 0.0)
 
 
 def parity_sample(lib, torch, m, r, v, tau, rows):
