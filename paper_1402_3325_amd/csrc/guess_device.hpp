@@ -61,14 +61,52 @@ constexpr int DEFER_CAP = 16; // listed pairs per 64 x 64 tile and step
 
 // Domain test without divisions or square roots: tau'^2 = u^2 mu / r0,
 // b' >= b_lo  <=>  beta r0 >= b_lo mu,  e'^2 <= e_hi^2  <=>  eta^2 <= e_hi^2 mu r0.
-SAKURA_HD inline bool guess_domain(const GuessNet &g, double mu, double r0, double r0inv,
-                                   double eta, double beta, double u)
+SAKURA_HD inline bool in_domain(double tau2_lo, double tau2_hi, double b_lo, double e2_hi,
+                                double mu, double r0, double r0inv, double eta, double beta,
+                                double u)
 {
     const double mr = mu * r0inv;
     const double tau2 = u * u * mr;
-    return mu > 0.0 && u != 0.0 && tau2 >= g.tau2_lo && tau2 <= g.tau2_hi &&
-           beta * r0 >= g.b_lo * mu && eta * eta <= g.e2_hi * mu * r0;
+    return mu > 0.0 && u != 0.0 && tau2 >= tau2_lo && tau2 <= tau2_hi &&
+           beta * r0 >= b_lo * mu && eta * eta <= e2_hi * mu * r0;
 }
+SAKURA_HD inline bool guess_domain(const GuessNet &g, double mu, double r0, double r0inv,
+                                   double eta, double beta, double u)
+{
+    return in_domain(g.tau2_lo, g.tau2_hi, g.b_lo, g.e2_hi, mu, r0, r0inv, eta, beta, u);
+}
+
+#ifndef SAKURA_HOST_ONLY
+// Plain starter with domain membership (statistics of the pairs a network
+// would start), used out of line by kepler_flow_domain.
+struct DomainOnly {
+    static constexpr bool active = true;
+    double tau2_lo, tau2_hi, b_lo, e2_hi;
+    bool in_dom = false;
+
+    __device__ int start(double, double mu, double r0, double r0inv, double eta, double beta,
+                         double u, double, double, double &)
+    {
+        in_dom = in_domain(tau2_lo, tau2_hi, b_lo, e2_hi, mu, r0, r0inv, eta, beta, u);
+        return START_PLAIN;
+    }
+    __device__ void done(double, double, double, double, double, double, double, int) {}
+};
+
+// The plain flow with domain membership in the result (PairFlow::in_dom),
+// kept out of line like the plain kepler_flow; all arguments are values, so
+// the policy stays in registers.
+__device__ __attribute__((noinline)) PairFlow
+kepler_flow_domain(double tau, double mu, double x0, double x1, double x2, double w0, double w1,
+                   double w2, double r0sq, const KeplerParams &kp, double tau2_lo,
+                   double tau2_hi, double b_lo, double e2_hi)
+{
+    DomainOnly pol{tau2_lo, tau2_hi, b_lo, e2_hi};
+    PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, pol);
+    f.in_dom = pol.in_dom;
+    return f;
+}
+#endif
 
 // The eight raw inputs (before shift and scale).
 SAKURA_HD inline void guess_inputs(double mu, double r0, double r0inv, double eta, double beta,
@@ -226,10 +264,7 @@ __device__ inline double net_starter(const GuessNet &g, double tau, double mu, d
 // membership recorded; MODE 2: the network's starter (s_net, computed ahead
 // by net_starter) for pairs in the domain; MODE 3: plain starter, and every
 // pair in the domain appends a harvest row {8 raw inputs, y = log(s r0 / t) at
-// the converged root, i, j, evaluations} (the last three as int32 bits);
-// MODE 4: pairs in the domain are skipped and listed for k_deferred (up to
-// the wave's remaining list capacity, *room; beyond it they are solved here
-// with the plain starter).
+// the converged root, i, j, evaluations} (the last three as int32 bits).
 template <int MODE>
 struct NetGuess {
     static constexpr bool active = true;
@@ -237,38 +272,17 @@ struct NetGuess {
     int pi, pj;          // particle indices (harvest rows)
     bool in_dom = false; // the pair lies in the network's domain
     bool used = false;   // the network's starter replaced the plain one
-    bool deferred = false; // MODE 4: skipped here, listed for the deferred kernel
-    int slot = 0;        // MODE 4: position in the wave's list
     double s_start = 0.0, s_root = 0.0;
     double s_net;        // MODE 2: the network's starter from net_starter (NaN: none)
-    int *room;           // MODE 4: list slots left (wave-uniform)
 
-    __device__ NetGuess(const GuessNet &net, int i, int j, double snet = __builtin_nan(""),
-                        int *room_left = nullptr)
-        : g(net), pi(i), pj(j), s_net(snet), room(room_left) {}
+    __device__ NetGuess(const GuessNet &net, int i, int j, double snet = __builtin_nan(""))
+        : g(net), pi(i), pj(j), s_net(snet) {}
 
     __device__ int start(double t, double mu, double r0, double r0inv, double eta,
                          double beta, double u, double lo, double hi, double &s)
     {
         in_dom = guess_domain(g, mu, r0, r0inv, eta, beta, u);
         s_start = s;
-        if (MODE == 4) {
-            const unsigned long long mask = __ballot(in_dom);
-            if (!mask) return START_PLAIN;
-            const int lane = threadIdx.x & 63;
-            const unsigned long long below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
-            // (__popcll is unsigned: keep the arithmetic in int)
-            const int rank = (int)__popcll(below);
-            const int total = (int)__popcll(mask);
-            const int avail = *room;
-            *room = avail > total ? avail - total : 0;
-            if (in_dom && rank < avail) {
-                deferred = true;
-                slot = rank;
-                return START_SKIP;
-            }
-            return START_PLAIN;
-        }
         if (MODE != 2 || !in_dom || !(s_net > lo && s_net < hi)) return START_PLAIN; // also NaN
         s = s_net;
         s_start = s_net;

@@ -151,8 +151,9 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 // s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
 // Partial sums go to part[I][J] (i side) and part[J][I] (j side).
 // MODE selects the starter: 0 plain; with a loaded network 1 plain with
-// domain statistics, 3 plain with harvest rows, 4 pairs in the network's
-// domain listed for k_deferred (which starts them from the network).
+// domain statistics, 3 plain with harvest rows, 4 pairs that may lie in the
+// network's domain listed for k_deferred (which starts those in the domain
+// from the network) and the rest solved plainly.
 template <bool HIST, int MODE>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
@@ -211,11 +212,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
     for (int s = s0; s < s1; ++s) {
         const int q = (lane + s) & (TILE - 1);
-        // With a starter policy the particle data are read from LDS at every
-        // use and the relative state is formed again after the solve
-        // (compiler-only fences): that policy's extra live state would
-        // otherwise push the loop past 128 VGPRs.  The plain loop keeps it.
-        if (MODE != 0) asm volatile("" ::: "memory");
+        // In harvest mode the particle data are read from LDS at every use and
+        // the relative state is formed again after the solve (compiler-only
+        // fences): its inlined policy's extra live state would otherwise push
+        // the loop past 128 VGPRs.  The other modes keep it.
+        if (MODE == 3) asm volatile("" ::: "memory");
         const double mi = si[6][lane], mj = sj[6][q];
         const double msum = mi + mj;
         const bool act = valid_i && (q < nj) && (msum > 0.0) &&
@@ -231,25 +232,44 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         bool live = act && !collide;
         // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
         kep::PairFlow f;
-        if constexpr (MODE == 0) {
+        if constexpr (MODE == 4) {
+            // Pairs that may lie in the network's domain (a necessary condition
+            // from the unreduced tau) are listed for k_deferred while the tile's
+            // list has room, and skipped here; the rest take the plain solve.
+            const bool cand = live && kep::pair_may_qualify(net, tau, G * msum, r0sq);
+            const unsigned long long mask = __ballot(cand);
+            if (mask) {
+                const unsigned long long below =
+                    lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+                const int rank = (int)__popcll(below), total = (int)__popcll(mask);
+                if (cand && rank < room) {
+                    net.defer_pairs[(size_t)blockIdx.x * kep::DEFER_CAP +
+                                    (kep::DEFER_CAP - room) + rank] = make_int2(ig, J * TILE + q);
+                    live = false; // solved, and counted, by k_deferred
+                }
+                room = room > total ? room - total : 0;
+            }
+        }
+        if constexpr (MODE == 0 || MODE == 4) {
             f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
                                  w2, live ? r0sq : 1.0, kp);
-        } else {
-            const int listed = kep::DEFER_CAP - room;
-            kep::NetGuess<MODE> gp(net, ig, J * TILE + q, __builtin_nan(""), &room);
+        } else if constexpr (MODE == 1) {
+            f = kep::kepler_flow_domain(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
+                                        w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
+                                        net.tau2_hi, net.b_lo, net.e2_hi);
+            const bool dom = live && f.in_dom;
+            gc.dom += __popcll(__ballot(dom));
+            dom_it += dom ? (unsigned)f.iters : 0u;
+        } else { // harvest
+            kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
             f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
                                  w2, live ? r0sq : 1.0, kp, gp);
-            if (MODE == 4 && gp.deferred) {
-                net.defer_pairs[(size_t)blockIdx.x * kep::DEFER_CAP + listed + gp.slot] =
-                    make_int2(ig, J * TILE + q);
-                live = false; // solved, and counted, by k_deferred
-            }
             const bool dom = live && gp.in_dom;
             gc.dom += __popcll(__ballot(dom));
             dom_it += dom ? (unsigned)f.iters : 0u;
         }
 
-        if (MODE != 0) { // the same relative state again, bitwise
+        if (MODE == 3) { // the same relative state again, bitwise
             asm volatile("" ::: "memory");
             w0 = si[3][lane] - sj[3][q];
             w1 = si[4][lane] - sj[4][q];
@@ -316,9 +336,10 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
 }
 
-// The pairs of the network's domain that k_pairs listed (MODE 4): the list of
-// one tile per wavefront, started from the network's value (fused MFMA
-// evaluation) and solved with the same root search; their weighted increments
+// The pairs that k_pairs listed (MODE 4): the list of one tile per wavefront;
+// those in the network's domain are started from its value (fused MFMA
+// evaluation), the others from the plain starter, and all take the same root
+// search; their weighted increments
 // are added to the tile's partial sums in list order, one lane per component,
 // so the result does not depend on the order in which tiles are taken.
 // Persistent: every wave leaves once the list is exhausted.
