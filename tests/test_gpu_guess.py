@@ -438,3 +438,92 @@ def test_learned_batched_matches_oracle(torch, lib, oracle):
         rr, vr = oracle.step(m[a:b], r[a:b].copy(), v[a:b].copy(), tau[s])
         er, ev = step_error(R[a:b], V[a:b], rr, vr, r[a:b], v[a:b])
         assert er <= TOL and ev <= TOL, (s, er, ev)
+
+
+# --------------------------------------------------------------------------
+# edges of the learned-starter API
+
+@pytest.mark.parametrize("n", [1, 63, 65])
+def test_guess_eval_ragged_sizes(torch, lib, oracle, n):
+    from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
+    mu, X, W, T = kepler_problems(n + 12, 27)  # rounds down to whole kinds
+    mu, X, W, T = mu[:n], X[:n], W[:n], T[:n]
+    F, Y, D = oracle_samples(oracle, *kepler_problems(600, 28))
+    lib.set_guess_model(make_model(np.random.default_rng(9), F, D))
+    try:
+        for g in (GUESS_ANALYTIC, GUESS_LEARNED):
+            lib.set_guess(g)
+            s0, s1, info = run_eval(torch, lib, mu, X, W, T)
+            assert s1.shape == (n,) and np.all(info & 8) and np.all(np.isfinite(s1))
+            # every problem's root, whichever starter, in the oracle's terms:
+            # y = log(s r0 / t) for the problems of the domain
+            F2, Y2, D2 = oracle_samples(oracle, mu, X, W, T)
+            r0 = np.linalg.norm(X, axis=1)
+            t = reduced_time(mu, X, W, T)
+            k = D2 & ~near_boundary(F2)
+            np.testing.assert_allclose(np.log(s1[k] * r0[k] / t[k]), Y2[k], rtol=0, atol=1e-10)
+    finally:
+        lib.set_guess(GUESS_ANALYTIC)
+        lib.set_guess_model(None)
+
+
+def test_harvest_respects_capacity(torch, lib):
+    m, r, v = small_cluster(202, n_stars=511)
+    cap = 5
+    buf = torch.full((cap + 3, 12), -7.0, dtype=torch.float32, device="cuda")
+    mt, rt, vt = _dev(torch, m, r, v)
+    lib.harvest_begin(buf[:cap], DOMAIN)
+    st = lib.evolve(mt, rt, vt, 1.0 / 2048, 2, stats=True)
+    offered = lib.harvest_end()
+    assert offered == st["guess_domain_pairs"] > cap  # counted, though dropped
+    B = buf.cpu().numpy()
+    assert np.all(B[cap:] == -7.0)  # nothing written past the buffer
+    assert np.all(np.isfinite(B[:cap, :9]))
+
+
+def test_training_is_deterministic(torch, lib):
+    rows = torch.zeros((60000, 12), dtype=torch.float32, device="cuda")
+    m, r, v = small_cluster(203, n_stars=2047)
+    mt, rt, vt = _dev(torch, m, r, v)
+    lib.harvest_begin(rows, DOMAIN)
+    lib.evolve(mt, rt, vt, 1.0 / 2048, 60)
+    n = min(lib.harvest_end(), rows.shape[0])
+    assert n > 1000
+    a, ha = lib.mlp_fit(rows[:n], DOMAIN, epochs=3, batch=1024, seed=5)
+    b, hb = lib.mlp_fit(rows[:n], DOMAIN, epochs=3, batch=1024, seed=5)
+    c, hc = lib.mlp_fit(rows[:n], DOMAIN, epochs=3, batch=1024, seed=6)
+    pa, pb, pc = (np.ctypeslib.as_array(x.params) for x in (a, b, c))
+    np.testing.assert_array_equal(pa, pb)
+    assert ha == hb
+    assert not np.array_equal(pa, pc)
+
+
+def test_model_and_mode_errors(torch, lib):
+    from paper_1402_3325_amd.sakura import (EINVAL, ENOMODEL, GUESS_ANALYTIC, GUESS_LEARNED,
+                                            Sakura, SakuraError)
+    F, Y, D = oracle_samples(__import__("oracle"), *kepler_problems(300, 29))
+    bad = make_model(np.random.default_rng(10), F, D)
+    bad["params"] = bad["params"].copy()
+    bad["params"][7] = np.nan
+    with pytest.raises(SakuraError) as e:
+        lib.set_guess_model(bad)
+    assert e.value.code == EINVAL
+    empty = make_model(np.random.default_rng(10), F, D)
+    empty["domain"] = [2.0, 1.0, -1.0, 3.0]  # tau_hi < tau_lo
+    with pytest.raises(SakuraError) as e:
+        lib.set_guess_model(empty)
+    assert e.value.code == EINVAL
+    h = Sakura(0, guess=GUESS_LEARNED)  # no model loaded
+    m, r, v = small_cluster(204, n_stars=63)
+    mt, rt, vt = _dev(torch, m, r, v)
+    r_before = rt.clone()
+    with pytest.raises(SakuraError) as e:
+        h.evolve(mt, rt, vt, 1.0 / 2048, 1)
+    assert e.value.code == ENOMODEL
+    assert torch.equal(rt, r_before)
+    h.set_guess(GUESS_ANALYTIC)
+    h.evolve(mt, rt, vt, 1.0 / 2048, 1)
+    with pytest.raises(SakuraError) as e:
+        h.set_guess(7)
+    assert e.value.code == EINVAL
+    h.close()
