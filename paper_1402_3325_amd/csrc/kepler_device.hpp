@@ -190,18 +190,21 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
         st.r = r;
         return 1;
     }
-    // Converged at s - ds: the error left after the step, estimated from the
-    // derivatives of t(s) -- the Newton term |t2| ds^2 / 2r and the cubic
-    // terms (|t3| / r + (t2 / r)^2) |ds|^3, with t2, t3 the second and third
-    // derivatives -- is below tol |s - ds| (tested without divisions).  The
-    // G-functions are then carried to s - ds by their Taylor series
-    // (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of being evaluated again.
+    // Converged at s - ds: the step taken (Laguerre's, or Halley's) has a
+    // cubic error, e_new ~ C e^3 with |C| <= (t2 / r)^2 + |t3| / r for both
+    // (t2, t3 the second and third derivatives of t(s); Laguerre's order-5
+    // constant differs from Halley's t2^2/4r^2 - t3/6r by 5 t2^2 / 32 r^2), so
+    // once the step is small (|ds| <= 2^-16 |s - ds|, where that expansion
+    // holds) the error left is bounded by (|t3| r + t2^2) |ds|^3 / r^2, and
+    // the step is accepted when that is below tol |s - ds| / 4 (tested without
+    // divisions).  The G-functions are then carried to s - ds by their Taylor
+    // series (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of being
+    // evaluated again.
     const double sn = s - ds;
     const double asn = fabs(sn);
     const double aFpp = fabs(Fpp);
     const double Fppp = fma(zeta, G0, -beta * eta * G1);
-    const double ads2 = ads * ads;
-    const double err_r2 = fma(aFpp * ads2, r, ads2 * ads * fma(fabs(Fppp), r, aFpp * aFpp));
+    const double err_r2 = ads * ads * ads * fma(fabs(Fppp), r, aFpp * aFpp);
     if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * r * r && sn >= st.lo &&
         sn <= st.hi) {
         const double d = -ds;
@@ -250,10 +253,17 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
 
 // Plain starter and bracket of the root search on t(s) = t.
 //
-// Starter: the cubic reversion of t = r0 s + eta s^2/2 + zeta s^3/6.  When its
-// corrections dominate the series is no guide: start from the free drift u
-// instead, or, deep in the hyperbolic regime (-beta u^2 > 1), from the
-// inversion of t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3), k = sqrt(-beta).
+// Starter: the reversion of the Taylor series of t(s) = r0 s + eta s^2/2 +
+// zeta s^3/6 - beta eta s^4/24 - beta zeta s^5/120 + ..., i.e. with
+// u = t / r0 and A_k = t^(k)(0) / (k! r0),
+//   s = u - A2 u^2 + (2 A2^2 - A3) u^3 + (5 A2 A3 - A4 - 5 A2^3) u^4
+//         + (6 A2 A4 + 3 A3^2 + 14 A2^4 - A5 - 21 A2^2 A3) u^5,
+// to third order where the corrections are below 2^-9 (the reversion error is
+// then about their square, which the first evaluation accepts) and to fifth
+// order otherwise.  When its corrections dominate the series is no
+// guide: start from the free drift u instead, or, deep in the hyperbolic
+// regime (-beta u^2 > 1), from the inversion of
+// t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3), k = sqrt(-beta).
 //
 // Bracket: the root has the sign of t since t(0) = 0 and t(s) increases.  For
 // unbound motion the far end stays open (+-1e300), except that an unbound pair
@@ -265,8 +275,20 @@ SAKURA_HD inline void analytic_start(double t, double u, double r0, double r0inv
 {
     const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
     const double corr1 = -0.5 * eta * r0inv * u, corr2 = c3s * u * u;
-    s = u * (1.0 + corr1 + corr2);
-    if (fabs(corr1) + fabs(corr2) > 0.5) {
+    const double csum = fabs(corr1) + fabs(corr2);
+    double corr34 = 0.0;
+    if (csum > 0x1p-9) {
+        const double A2 = 0.5 * eta * r0inv, A3 = (1.0 / 6.0) * zeta * r0inv;
+        const double A4 = (-1.0 / 24.0) * beta * eta * r0inv;
+        const double A5 = (-1.0 / 120.0) * beta * zeta * r0inv;
+        const double A22 = A2 * A2;
+        const double k4 = fma(5.0 * A2, A3 - A22, -A4);
+        const double k5 = fma(A2, fma(6.0, A4, A2 * fma(14.0, A22, -21.0 * A3)),
+                              fma(3.0 * A3, A3, -A5));
+        corr34 = u * u * u * fma(k5, u, k4);
+    }
+    s = u * (1.0 + corr1 + corr2 + corr34);
+    if (csum > 0.5) {
         s = u;
         if (beta < 0.0 && -beta * u * u > 1.0) {
             const double k = sqrt(-beta);
