@@ -142,9 +142,10 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 
 // All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
 //
-// Lane l holds particle i = 64 I + l; block J sits in LDS (read only).  In
-// sub-step s lane l takes the pair (i, 64 J + ((l + s) mod 64)), so within a
-// sub-step every lane touches a different j.  The j-side sums (Newton's third
+// Lane l holds particle i = 64 I + l and its i-side sums in registers; block
+// J sits in LDS (read only).  In sub-step s lane l takes the pair
+// (i, 64 J + ((l + s) mod 64)), so within a sub-step every lane touches a
+// different j.  The j-side sums (Newton's third
 // law) live in registers and follow their j: after each sub-step every lane
 // takes the sums of lane l + 1, which is the j it meets next.  No atomics, no
 // LDS writes and no barrier inside the loop.  The diagonal tile runs
@@ -173,8 +174,6 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const double *XH = S + 7 * (size_t)np;
 
     __shared__ double sj[7][TILE]; // x y z vx vy vz m of block J; later the j-side sums
-    __shared__ double si[7][TILE]; // the same for block I (each lane reads its own slot)
-    __shared__ double sacc[6][TILE]; // i-side sums, one slot per lane
     __shared__ unsigned shist[HIST ? 32 : 1];
 
     const int jg = J * TILE + lane;
@@ -186,14 +185,10 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     sj[4][lane] = V[np + jg];
     sj[5][lane] = V[2 * (size_t)np + jg];
     sj[6][lane] = M[jg];
-    si[0][lane] = XH[ig];
-    si[1][lane] = XH[np + ig];
-    si[2][lane] = XH[2 * (size_t)np + ig];
-    si[3][lane] = V[ig];
-    si[4][lane] = V[np + ig];
-    si[5][lane] = V[2 * (size_t)np + ig];
-    si[6][lane] = M[ig];
-    for (int c = 0; c < 6; ++c) sacc[c][lane] = 0.0;
+    // particle i and its sums stay in registers
+    const double xi[7] = {XH[ig], XH[np + ig], XH[2 * (size_t)np + ig], V[ig], V[np + ig],
+                          V[2 * (size_t)np + ig], M[ig]};
+    double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (HIST && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
@@ -217,16 +212,16 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         // fences): its inlined policy's extra live state would otherwise push
         // the loop past 128 VGPRs.  The other modes keep it.
         if (MODE == 3) asm volatile("" ::: "memory");
-        const double mi = si[6][lane], mj = sj[6][q];
+        const double mi = xi[6], mj = sj[6][q];
         const double msum = mi + mj;
         const bool act = valid_i && (q < nj) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         // relative state and the pair back-drift of eq. (17) by tau/2
-        double w0 = si[3][lane] - sj[3][q], w1 = si[4][lane] - sj[4][q],
-               w2 = si[5][lane] - sj[5][q];
-        double x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
-        double x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
-        double x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
+        double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q],
+               w2 = xi[5] - sj[5][q];
+        double x0 = fma(-h, w0, xi[0] - sj[0][q]);
+        double x1 = fma(-h, w1, xi[1] - sj[1][q]);
+        double x2 = fma(-h, w2, xi[2] - sj[2][q]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
         bool live = act && !collide;
@@ -271,12 +266,12 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
 
         if (MODE == 3) { // the same relative state again, bitwise
             asm volatile("" ::: "memory");
-            w0 = si[3][lane] - sj[3][q];
-            w1 = si[4][lane] - sj[4][q];
-            w2 = si[5][lane] - sj[5][q];
-            x0 = fma(-h, w0, si[0][lane] - sj[0][q]);
-            x1 = fma(-h, w1, si[1][lane] - sj[1][q]);
-            x2 = fma(-h, w2, si[2][lane] - sj[2][q]);
+            w0 = xi[3] - sj[3][q];
+            w1 = xi[4] - sj[4][q];
+            w2 = xi[5] - sj[5][q];
+            x0 = fma(-h, w0, xi[0] - sj[0][q]);
+            x1 = fma(-h, w1, xi[1] - sj[1][q]);
+            x2 = fma(-h, w2, xi[2] - sj[2][q]);
         }
         // increments of eq. (26) minus the starting relative state
         const double a = fma(-h, f.fdot, f.fm1);
@@ -289,7 +284,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const double wgt_i = mj * inv, wgt_j = mi * inv;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            sacc[c][lane] = fma(wgt_i, d[c], sacc[c][lane]);
+            ai[c] = fma(wgt_i, d[c], ai[c]);
             jac[c] = from_next_lane(fma(-wgt_j, d[c], jac[c]));
         }
         it_sum += live ? f.iters : 0;
@@ -311,11 +306,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const size_t cs = TILE; // component stride inside a partial
     double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
     if (diag) {
-        for (int c = 0; c < 6; ++c) pij[c * cs] = sacc[c][lane] + sj[c][lane];
+        for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + sj[c][lane];
     } else {
         double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
         for (int c = 0; c < 6; ++c) {
-            pij[c * cs] = sacc[c][lane];
+            pij[c * cs] = ai[c];
             pji[c * cs] = sj[c][lane];
         }
     }
