@@ -139,8 +139,9 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                 const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
                                      fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
                                      fma(f.fdot, x2, f.gdm1 * w2)};
-                const double inv = live ? kep::rcp_refined(msum) : 0.0;
-                const double wgt_i = mj * inv, wgt_j = mi * inv;
+                // m_j / (m_i + m_j) and m_i / (m_i + m_j) times the flow's 1/mu;
+                // lanes without a pair have zero coefficients (they solve tau = 0)
+                const double wgt_i = G * mj, wgt_j = G * mi;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     acc[c] = fma(wgt_i, d[c], acc[c]);

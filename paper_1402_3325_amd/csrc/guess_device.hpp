@@ -244,12 +244,8 @@ __device__ inline double net_starter(const GuessNet &g, double tau, double mu, d
     const double eta = fma(x0, w0, fma(x1, w1, x2 * w2));
     const double vsq = fma(w0, w0, fma(w1, w1, w2 * w2));
     const double beta = fma(2.0 * mu, r0inv, -vsq);
-    double t = tau;
-    if (beta > 0.0) {
-        const double ib = rsqrt_refined(beta);
-        const double P = 6.283185307179586 * mu * ib * ib * ib;
-        if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
-    }
+    double s_half, tshift_mu;
+    const double t = reduce_time(tau, mu, beta, s_half, tshift_mu); // as kepler_flow does
     const double u = t * r0inv;
     const bool dom = ok && guess_domain(g, mu, r0, r0inv, eta, beta, u);
     float f[NET_IN];

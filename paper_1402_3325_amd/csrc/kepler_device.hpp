@@ -73,15 +73,14 @@ SAKURA_HD inline void stumpff23(double z, double &c2, double &c3)
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates
-// (v_rcp_f64 / v_rsq_f64, relative error near 2^-23) refined by Newton steps:
-// one step gives about 2^-46, two steps the last-bit accuracy of a division.
+// (v_rcp_f64 / v_rsq_f64, relative error e near 2^-23) refined by one step of
+// third order: y (1 + e + e^2) resp. y (1 + e/2 + 3 e^2/8) leave an error of
+// order e^3, below the rounding of the result.
 SAKURA_HD inline double rcp_refined(double x)
 {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 SAKURA_HD inline double rcp_step(double x) // about 2^-46
 {
@@ -90,11 +89,9 @@ SAKURA_HD inline double rcp_step(double x) // about 2^-46
 }
 SAKURA_HD inline double rsqrt_refined(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 SAKURA_HD inline double sqrt_step(double x) // about 2^-46, x >= 0
 {
@@ -117,7 +114,11 @@ SAKURA_HD inline void stumpff23_small(double z, double &c2, double &c3)
 #endif
 
 struct PairFlow {
-    double fm1, gmt, fdot, gdm1; // f-1, g-tau, fdot, gdot-1
+    // Lagrange coefficients as differences from the free drift, per unit mu:
+    // (f-1)/mu, (g-tau)/mu, fdot/mu, (gdot-1)/mu.  All four are proportional
+    // to mu, so the caller's weights m_j/(m_i+m_j) become G m_j, with no
+    // division per pair.
+    double fm1, gmt, fdot, gdm1;
     int iters;
     bool converged;
     bool safeguarded; // a bisection or bracket-expansion step was needed
@@ -133,98 +134,160 @@ struct KepIter {
     bool safeguarded;
 };
 
-// One evaluation of t(s) - tau at st.s and its Laguerre step (order 5).
-// Returns 1 when st.s is the root (G-functions and r left at st.s), 2 when
-// st.s - ds is (G-functions carried there by their Taylor series), 0 when the
-// search goes on from the new st.s.
-//
-// TIER says what every lane of the wavefront has in common: 0 nothing;
-// 1 |z| <= 2^-10 (four-term Stumpff series); 2 |z| <= 2^-14, where three terms
-// of each series leave a truncation below 2^-56, the Laguerre step is taken in
-// its Halley form F r / (r^2 - F F''/2) while |F F''| <= 2^-22 r^2 (the two
-// agree to a relative q^2/10, q = 5 F F'' / 4 r^2, i.e. below 2^-42), and an
-// accepted step moves the G-functions by their Taylor series to first order
-// when |ds| <= 2^-28 |s| on every accepting lane, to second order when
-// |ds| <= 2^-18 |s| (the dropped terms are then below 3 (ds/s)^2 resp.
-// (ds/s)^3, i.e. below 2^-54 of each function), else to third order.
+// The quantities of one evaluation of t(s) - t at s, with c2(z), c3(z) of
+// z = beta s^2 evaluated by the tier every lane of the wavefront qualifies
+// for: 0 nothing; 1 |z| <= 2^-10 (four-term series); 2 |z| <= 2^-14, where
+// three terms of each series leave a truncation below 2^-56.
+struct KepEval {
+    double G0, G1, G2, G3, F, r, Fpp;
+};
 template <int TIER>
-SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double zeta,
-                                    double r0, double t, double tol)
+SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double zeta, double r0,
+                                     double t)
 {
-    const double s = st.s;
-    const double z = beta * s * s;
+    const double s2 = s * s;
+    const double z = beta * s2;
     double c2, c3;
     if (TIER == 2) {
-        c2 = fma(fma(z, 1.0 / 720.0, -1.0 / 24.0), z, 0.5);
-        c3 = fma(fma(z, 1.0 / 5040.0, -1.0 / 120.0), z, 1.0 / 6.0);
+        // 1/2 - z/24 + z^2/720 and 1/6 - z/120 + z^2/5040, written with one
+        // non-trivial constant per operation (a VALU operation reads at most
+        // one scalar), which saves the moves of constants into vector registers
+        c2 = fma((1.0 / 720.0) * z, z - 30.0, 0.5);
+        c3 = fma((1.0 / 5040.0) * z, z - 42.0, 1.0 / 6.0);
     } else if (TIER == 1) {
         stumpff23_small(z, c2, c3);
     } else {
         stumpff23(z, c2, c3);
     }
-    const double s2 = s * s;
-    const double G1 = s * fma(-z, c3, 1.0);
-    const double G2 = s2 * c2;
-    const double G3 = s2 * s * c3;
-    const double G0 = fma(-z, c2, 1.0);
-    const double F = fma(r0, s, fma(eta, G2, fma(zeta, G3, -t)));
-    const double r = fma(eta, G1, fma(zeta, G2, r0));
-    const double Fpp = fma(eta, G0, zeta * G1);
-    if (F < 0.0) st.lo = s;
-    else st.hi = s;
-    const double FFpp = F * Fpp;
-    double ds;
-    if (TIER == 2 && fabs(FFpp) <= 0x1p-22 * (r * r)) {
-        ds = F * r * rcp_step(fma(-0.5, FFpp, r * r));
-    } else {
-        const double disc = fma(16.0 * r, r, -20.0 * FFpp);
-        ds = 5.0 * F * rcp_step(r + sqrt_step(fabs(disc)));
+    KepEval e;
+    e.G1 = s * fma(-z, c3, 1.0);
+    e.G2 = s2 * c2;
+    e.G3 = s2 * s * c3;
+    e.G0 = fma(-z, c2, 1.0);
+    e.F = fma(r0, s, fma(eta, e.G2, fma(zeta, e.G3, -t)));
+    e.r = fma(eta, e.G1, fma(zeta, e.G2, r0));
+    e.Fpp = fma(eta, e.G0, zeta * e.G1);
+    return e;
+}
+
+// Laguerre step of order 5 at an evaluation; with HALLEY (every lane has
+// |z| <= 2^-14) it is taken in its Halley form F r / (r^2 - F F''/2) while
+// |F F''| <= 2^-22 r^2: the two agree to a relative q^2/10, q = 5 F F'' / 4 r^2,
+// i.e. below 2^-42.
+template <bool HALLEY>
+SAKURA_HD inline double laguerre_step(const KepEval &e)
+{
+    const double FFpp = e.F * e.Fpp;
+    if (HALLEY && fabs(FFpp) <= 0x1p-22 * (e.r * e.r))
+        return e.F * e.r * rcp_step(fma(-0.5, FFpp, e.r * e.r));
+    const double disc = fma(16.0 * e.r, e.r, -20.0 * FFpp);
+    return 5.0 * e.F * rcp_step(e.r + sqrt_step(fabs(disc)));
+}
+
+// Acceptance of the root s - ds after a step from s: the step taken
+// (Laguerre's, or Halley's) has a cubic error, e_new ~ C e^3 with
+// |C| <= (t2 / r)^2 + |t3| / r for both (t2, t3 the second and third
+// derivatives of t(s); Laguerre's order-5 constant differs from Halley's
+// t2^2/4r^2 - t3/6r by 5 t2^2 / 32 r^2), so once the step is small
+// (|ds| <= 2^-16 |s - ds|, where that expansion holds) the error left is
+// bounded by (|t3| r + t2^2) |ds|^3 / r^2, and the step is accepted when that
+// is below tol |s - ds| / 4 (tested without divisions).
+SAKURA_HD inline bool step_accepted(const KepEval &e, double ds, double sn, double beta,
+                                    double eta, double zeta, double tol)
+{
+    const double ads = fabs(ds), asn = fabs(sn);
+    const double aFpp = fabs(e.Fpp);
+    const double Fppp = fma(zeta, e.G0, -beta * eta * e.G1);
+    const double err_r2 = ads * ads * ads * fma(fabs(Fppp), e.r, aFpp * aFpp);
+    return ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * e.r * e.r;
+}
+
+// The G-functions carried from s to s + d by their Taylor series
+// (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1), to third order, and r there.
+SAKURA_HD inline void taylor_shift3(KepIter &st, const KepEval &e, double d, double beta,
+                                    double eta, double zeta, double r0)
+{
+    const double d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
+    const double mbG1 = -beta * e.G1, mbG0 = -beta * e.G0;
+    st.G3 = fma(d3, e.G0, fma(d2, e.G1, fma(d, e.G2, e.G3)));
+    st.G2 = fma(d3, mbG1, fma(d2, e.G0, fma(d, e.G1, e.G2)));
+    st.G1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, e.G0, e.G1)));
+    st.r = fma(eta, st.G1, fma(zeta, st.G2, r0));
+}
+
+// First evaluation, at the starter.  Returns 2 when s - ds is the root
+// (st.s moved there, with the G-functions and r carried there by their Taylor
+// series), else 0 with st.s kept and F and the step ds left (signed) in
+// st.F_prev and st.ds_prev for kepler_search to go on from.  The root is taken
+// when the step is below tol |s| (or F = 0), or when the step is accepted by
+// its error bound; no bracket is consulted: t(s) increases strictly (r > 0),
+// so the root is unique.  Every lane forms the carried G-functions (those that
+// go on do not use them), so the common path has no divergent writes.  In
+// tier 2 they are carried to first order when |ds| <= 2^-28 |s - ds| on every
+// taking lane, to second order when |ds| <= 2^-18 |s - ds| (the dropped terms
+// are then below 3 (ds/s)^2 resp. (ds/s)^3, i.e. below 2^-54 of each
+// function), else, as in the other tiers, to third order.
+template <int TIER>
+SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double zeta, double r0,
+                                  double t, double tol)
+{
+    const double s = st.s;
+    const KepEval e = kepler_eval<TIER>(s, beta, eta, zeta, r0, t);
+    const double ds = laguerre_step<TIER == 2>(e);
+    const double ads = fabs(ds);
+    const double sn = s - ds;
+    const bool done = ads <= tol * fabs(s) || e.F == 0.0 ||
+                      step_accepted(e, ds, sn, beta, eta, zeta, tol);
+    const double d = -ds, asn = fabs(sn);
+    double G3 = fma(d, e.G2, e.G3);
+    double G2 = fma(d, e.G1, e.G2);
+    double G1 = fma(d, e.G0, e.G1);
+    if (TIER != 2 || !SAKURA_WAVE_ALL(!done || ads <= 0x1p-28 * asn)) {
+        const double d2 = 0.5 * d * d;
+        const double mbG1 = -beta * e.G1;
+        G3 = fma(d2, e.G1, G3);
+        G2 = fma(d2, e.G0, G2);
+        G1 = fma(d2, mbG1, G1);
+        if (TIER != 2 || !SAKURA_WAVE_ALL(!done || ads <= 0x1p-18 * asn)) {
+            const double d3 = d2 * d * (1.0 / 3.0);
+            G3 = fma(d3, e.G0, G3);
+            G2 = fma(d3, mbG1, G2);
+            G1 = fma(d3, -beta * e.G0, G1);
+        }
     }
+    st.G1 = G1;
+    st.G2 = G2;
+    st.G3 = G3;
+    st.r = fma(eta, G1, fma(zeta, G2, r0));
+    st.s = done ? sn : s;
+    st.F_prev = e.F;
+    st.ds_prev = ds;
+    return done ? 2 : 0;
+}
+
+// A later evaluation (general tier), inside the bracket [st.lo, st.hi].
+// Returns 1 / 2 as kepler_first, or 0 with st.s moved to the next iterate.
+SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double zeta,
+                                    double r0, double t, double tol)
+{
+    const double s = st.s;
+    const KepEval e = kepler_eval<0>(s, beta, eta, zeta, r0, t);
+    if (e.F < 0.0) st.lo = s;
+    else st.hi = s;
+    const double ds = laguerre_step<false>(e);
     const double ads = fabs(ds), as = fabs(s);
     // Converged at s: the correction is below tol |s|, or it sits at the
     // rounding floor of F (tiny and no longer shrinking).
-    if (ads <= tol * as || F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * st.ds_prev)) {
-        st.G1 = G1;
-        st.G2 = G2;
-        st.G3 = G3;
-        st.r = r;
+    if (ads <= tol * as || e.F == 0.0 || (ads <= 1e-10 * as && ads >= 0.5 * st.ds_prev)) {
+        st.G1 = e.G1;
+        st.G2 = e.G2;
+        st.G3 = e.G3;
+        st.r = e.r;
         return 1;
     }
-    // Converged at s - ds: the step taken (Laguerre's, or Halley's) has a
-    // cubic error, e_new ~ C e^3 with |C| <= (t2 / r)^2 + |t3| / r for both
-    // (t2, t3 the second and third derivatives of t(s); Laguerre's order-5
-    // constant differs from Halley's t2^2/4r^2 - t3/6r by 5 t2^2 / 32 r^2), so
-    // once the step is small (|ds| <= 2^-16 |s - ds|, where that expansion
-    // holds) the error left is bounded by (|t3| r + t2^2) |ds|^3 / r^2, and
-    // the step is accepted when that is below tol |s - ds| / 4 (tested without
-    // divisions).  The G-functions are then carried to s - ds by their Taylor
-    // series (dG_k/ds = G_{k-1}, dG_0/ds = -beta G_1) instead of being
-    // evaluated again.
     const double sn = s - ds;
-    const double asn = fabs(sn);
-    const double aFpp = fabs(Fpp);
-    const double Fppp = fma(zeta, G0, -beta * eta * G1);
-    const double err_r2 = ads * ads * ads * fma(fabs(Fppp), r, aFpp * aFpp);
-    if (ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * r * r && sn >= st.lo &&
-        sn <= st.hi) {
-        const double d = -ds;
-        if (TIER == 2 && SAKURA_WAVE_ALL(ads <= 0x1p-28 * asn)) {
-            st.G3 = fma(d, G2, G3);
-            st.G2 = fma(d, G1, G2);
-            st.G1 = fma(d, G0, G1);
-        } else if (TIER == 2 && SAKURA_WAVE_ALL(ads <= 0x1p-18 * asn)) {
-            const double d2 = 0.5 * d * d;
-            st.G3 = fma(d2, G1, fma(d, G2, G3));
-            st.G2 = fma(d2, G0, fma(d, G1, G2));
-            st.G1 = fma(d2, -beta * G1, fma(d, G0, G1));
-        } else {
-            const double d2 = 0.5 * d * d, d3 = d2 * d * (1.0 / 3.0);
-            const double mbG1 = -beta * G1, mbG0 = -beta * G0;
-            st.G3 = fma(d3, G0, fma(d2, G1, fma(d, G2, G3)));
-            st.G2 = fma(d3, mbG1, fma(d2, G0, fma(d, G1, G2)));
-            st.G1 = fma(d3, mbG0, fma(d2, mbG1, fma(d, G0, G1)));
-        }
-        st.r = fma(eta, st.G1, fma(zeta, st.G2, r0));
+    if (step_accepted(e, ds, sn, beta, eta, zeta, tol) && sn >= st.lo && sn <= st.hi) {
+        taylor_shift3(st, e, -ds, beta, eta, zeta, r0);
         st.s = sn;
         return 2;
     }
@@ -233,7 +296,7 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     // progress down an exponential).  A crawl inside a bracket much wider
     // than the step doubles the step; otherwise bisect, and an open bracket
     // is expanded.
-    const bool stall = (fabs(F) > 0.5 * st.F_prev && ads > 1e-6 * as) ||
+    const bool stall = (fabs(e.F) > 0.5 * st.F_prev && ads > 1e-6 * as) ||
                        (ads > 0.5 * st.ds_prev && ads > 1e-3 * as);
     double next = sn;
     const bool inside = next >= st.lo && next <= st.hi;
@@ -246,16 +309,39 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
         st.safeguarded = true;
     }
     st.ds_prev = ads;
-    st.F_prev = fabs(F);
+    st.F_prev = fabs(e.F);
     st.s = next;
     return 0;
 }
 
-// Plain starter and bracket of the root search on t(s) = t.
-//
-// Starter: the reversion of the Taylor series of t(s) = r0 s + eta s^2/2 +
-// zeta s^3/6 - beta eta s^4/24 - beta zeta s^5/120 + ..., i.e. with
-// u = t / r0 and A_k = t^(k)(0) / (k! r0),
+// Period reduction: for a bound orbit (beta > 0) sqrt(beta) s is the change
+// of eccentric anomaly, so one period P = 2 pi mu / beta^(3/2) spans
+// s = 2 pi / sqrt(beta), and with |t| <= P/2 the root lies inside that span.
+// Returns the reduced time t; s_half bounds |s| (1e300 for unbound motion)
+// and tshift_mu = (t - tau) / mu.
+SAKURA_HD inline double reduce_time(double tau, double mu, double beta, double &s_half,
+                                    double &tshift_mu)
+{
+    double t = tau;
+    s_half = 1e300;
+    tshift_mu = 0.0;
+    if (beta > 0.0) {
+        const double ib = rsqrt_refined(beta);
+        s_half = 6.3 * ib; // just above 2 pi / sqrt(beta)
+        const double P_mu = 6.283185307179586 * ib * ib * ib;
+        const double P = P_mu * mu;
+        if (fabs(t) > 0.5 * P) {
+            const double k = rint(t * rcp_refined(P));
+            t -= P * k;
+            tshift_mu = -P_mu * k;
+        }
+    }
+    return t;
+}
+
+// Plain starter of the root search on t(s) = t: the reversion of the Taylor
+// series of t(s) = r0 s + eta s^2/2 + zeta s^3/6 - beta eta s^4/24
+// - beta zeta s^5/120 + ..., i.e. with u = t / r0 and A_k = t^(k)(0) / (k! r0),
 //   s = u - A2 u^2 + (2 A2^2 - A3) u^3 + (5 A2 A3 - A4 - 5 A2^3) u^4
 //         + (6 A2 A4 + 3 A3^2 + 14 A2^4 - A5 - 21 A2^2 A3) u^5,
 // to third order where the corrections are below 2^-9 (the reversion error is
@@ -264,40 +350,48 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
 // guide: start from the free drift u instead, or, deep in the hyperbolic
 // regime (-beta u^2 > 1), from the inversion of
 // t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3), k = sqrt(-beta).
-//
-// Bracket: the root has the sign of t since t(0) = 0 and t(s) increases.  For
-// unbound motion the far end stays open (+-1e300), except that an unbound pair
-// moving apart (eta sgn t >= 0) only grows in r, so t(s) >= r0 s and the root
-// lies within |u|.
-SAKURA_HD inline void analytic_start(double t, double u, double r0, double r0inv, double eta,
-                                     double zeta, double beta, double mu, double s_half,
-                                     double &s, double &lo, double &hi)
+// A starter beyond |s| <= s_half or of the wrong sign is replaced by u,
+// clamped to that bound.
+SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0inv, double eta,
+                                      double zeta, double beta, double mu, double s_half)
 {
-    const double c3s = (3.0 * eta * eta - zeta * r0) * (r0inv * r0inv) * (1.0 / 6.0);
-    const double corr1 = -0.5 * eta * r0inv * u, corr2 = c3s * u * u;
+    const double p = eta * r0inv;                 // 2 A2
+    const double A3 = (1.0 / 6.0) * (zeta * r0inv);
+    const double corr1 = -0.5 * (p * u);           // -A2 u
+    const double uu = u * u;
+    const double corr2 = fma(0.5 * p, p, -A3) * uu; // (2 A2^2 - A3) u^2
     const double csum = fabs(corr1) + fabs(corr2);
-    double corr34 = 0.0;
+    double corr = corr1 + corr2;
     if (csum > 0x1p-9) {
-        const double A2 = 0.5 * eta * r0inv, A3 = (1.0 / 6.0) * zeta * r0inv;
+        const double A2 = 0.5 * p;
         const double A4 = (-1.0 / 24.0) * beta * eta * r0inv;
         const double A5 = (-1.0 / 120.0) * beta * zeta * r0inv;
         const double A22 = A2 * A2;
         const double k4 = fma(5.0 * A2, A3 - A22, -A4);
         const double k5 = fma(A2, fma(6.0, A4, A2 * fma(14.0, A22, -21.0 * A3)),
                               fma(3.0 * A3, A3, -A5));
-        corr34 = u * u * u * fma(k5, u, k4);
+        corr += uu * u * fma(k5, u, k4);
     }
-    s = u * (1.0 + corr1 + corr2 + corr34);
+    double s = fma(u, corr, u);
     if (csum > 0.5) {
         s = u;
-        if (beta < 0.0 && -beta * u * u > 1.0) {
+        if (beta < 0.0 && -beta * uu > 1.0) {
             const double k = sqrt(-beta);
             const double D = fmax(fma(r0 * k, k, fma(eta * k, copysign(1.0, t), mu)), 1e-300);
             s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
         }
     }
-    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = u;
-    s = fmin(fmax(s, -s_half), s_half);
+    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = fmin(fmax(u, -s_half), s_half);
+    return s;
+}
+
+// Bracket of the root: it has the sign of t since t(0) = 0 and t(s)
+// increases.  For unbound motion the far end stays open (+-1e300), except
+// that an unbound pair moving apart (eta sgn t >= 0) only grows in r, so
+// t(s) >= r0 s and the root lies within |u|.
+SAKURA_HD inline void initial_bracket(double t, double u, double beta, double eta,
+                                      double s_half, double &lo, double &hi)
+{
     lo = (t > 0.0) ? 0.0 : -s_half;
     hi = (t > 0.0) ? s_half : 0.0;
     if (beta <= 0.0 && eta * t >= 0.0) {
@@ -319,24 +413,41 @@ struct NoGuess {
     SAKURA_HD void done(double, double, double, double, double, double, double, int) {}
 };
 
-// Root search from st until convergence or kp.max_iter evaluations; the first
-// evaluation takes the cheapest tier every lane of the wavefront qualifies for
-// (almost every pair of a star cluster converges there, in tier 2).
+// Root search from st.s until convergence or kp.max_iter evaluations.  The
+// first evaluation takes the cheapest tier every lane of the wavefront
+// qualifies for (almost every pair of a star cluster converges there, in
+// tier 2); the pairs that go on set up the bracket and continue in the
+// general tier.
 SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double zeta, double r0,
-                                   double t, const KeplerParams &kp, int &it)
+                                   double t, double u, double s_half, const KeplerParams &kp,
+                                   int &it)
 {
     const double z0 = fabs(beta * st.s * st.s);
     int res;
     if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
-        res = kepler_iterate<2>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol);
     else if (SAKURA_WAVE_ALL(z0 <= 0x1p-10))
-        res = kepler_iterate<1>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol);
     else
-        res = kepler_iterate<0>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol);
     it = 1;
-    while (res == 0 && it < kp.max_iter) {
-        ++it;
-        res = kepler_iterate<0>(st, beta, eta, zeta, r0, t, kp.tol);
+    if (res == 0) {
+        initial_bracket(t, u, beta, eta, s_half, st.lo, st.hi);
+        const double s = st.s, F = st.F_prev, ds = st.ds_prev;
+        if (F < 0.0) st.lo = s;
+        else st.hi = s;
+        double next = s - ds;
+        if (!(next >= st.lo && next <= st.hi)) {
+            next = (st.hi - st.lo < 1e299) ? 0.5 * (st.lo + st.hi) : 2.0 * s;
+            st.safeguarded = true;
+        }
+        st.ds_prev = fabs(ds);
+        st.F_prev = fabs(F);
+        st.s = next;
+        while (res == 0 && it < kp.max_iter) {
+            ++it;
+            res = kepler_iterate(st, beta, eta, zeta, r0, t, kp.tol);
+        }
     }
     return res;
 }
@@ -357,21 +468,14 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
     const double beta = fma(2.0 * mu, r0inv, -vsq);
     const double zeta = fma(-beta, r0, mu); // mu - beta r0 = d^2 r / ds^2 at s = 0
 
-    // sqrt(beta) s is the change of eccentric anomaly, so one period spans
-    // s = 2 pi / sqrt(beta); with |t| <= P/2 the root lies inside that span.
-    double t = tau;
-    double s_half = 1e300; // bound on |s| (bound orbits only)
-    if (beta > 0.0) {
-        const double ib = rsqrt_refined(beta);
-        s_half = 6.3 * ib; // just above 2 pi / sqrt(beta)
-        const double P = 6.283185307179586 * mu * ib * ib * ib;
-        if (fabs(t) > 0.5 * P) t -= P * rint(t * rcp_refined(P));
-    }
+    double s_half, tshift_mu;
+    const double t = reduce_time(tau, mu, beta, s_half, tshift_mu);
     const double u = t * r0inv;
-    double s, lo, hi;
-    analytic_start(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, s, lo, hi);
+    double s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half);
     bool replaced = false;
     if (Guess::active) {
+        double lo, hi;
+        initial_bracket(t, u, beta, eta, s_half, lo, hi);
         const int how = guess.start(t, mu, r0, r0inv, eta, beta, u, lo, hi, s);
         if (how == START_SKIP) {
             PairFlow z;
@@ -385,17 +489,16 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         replaced = how == START_REPLACED;
     }
 
-    KepIter st{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
+    KepIter st{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
     int it = 0;
-    int res = kepler_search(st, beta, eta, zeta, r0, t, kp, it);
+    int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, it);
     bool restarted = false;
     if (Guess::active && res == 0 && replaced) {
         restarted = true;
-        const double sh = beta > 0.0 ? 6.3 * rsqrt_refined(beta) : 1e300;
-        analytic_start(t, t * r0inv, r0, r0inv, eta, zeta, beta, mu, sh, s, lo, hi);
-        st = KepIter{s, lo, hi, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
+        s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half);
+        st = KepIter{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
         int it2 = 0;
-        res = kepler_search(st, beta, eta, zeta, r0, t, kp, it2);
+        res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, it2);
         it += it2;
     }
     PairFlow out;
@@ -406,12 +509,12 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
     const double G1 = st.G1, G2 = st.G2, G3 = st.G3, r = st.r;
     out.iters = it;
     if (Guess::active) guess.done(st.s, t, mu, r0, r0inv, eta, beta, it);
-    // Lagrange coefficients at the converged s.
+    // Lagrange coefficients at the converged s, per unit mu.
     const double rinv = rcp_refined(r);
-    out.fm1 = -mu * G2 * r0inv;
-    out.gmt = (t - tau) - mu * G3;
-    out.fdot = -mu * G1 * rinv * r0inv;
-    out.gdm1 = -mu * G2 * rinv;
+    out.fm1 = -G2 * r0inv;
+    out.gmt = tshift_mu - G3;
+    out.fdot = -G1 * rinv * r0inv;
+    out.gdm1 = -G2 * rinv;
     return out;
 }
 

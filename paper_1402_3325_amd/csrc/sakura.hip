@@ -114,16 +114,6 @@ __global__ void k_import(int n, int np, const double *__restrict__ m,
     }
 }
 
-// Value held by lane (l + 1) mod 64, for every lane l: a whole-wave rotate
-// (DPP wave_rol:1) applied to both halves of a double.
-__device__ inline double from_next_lane(double x)
-{
-    // every lane has a source under a full rotate, so no "old" value is needed
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x134, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
 // Blocks (I, J), I <= J, of tile t: off-diagonal tiles first (twice the work
 // of a diagonal one), column by column, then the diagonal.
 __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
@@ -143,14 +133,16 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 // All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
 //
 // Lane l holds particle i = 64 I + l and its i-side sums in registers; block
-// J sits in LDS (read only).  In sub-step s lane l takes the pair
+// J sits in LDS.  In sub-step s lane l takes the pair
 // (i, 64 J + ((l + s) mod 64)), so within a sub-step every lane touches a
-// different j.  The j-side sums (Newton's third
-// law) live in registers and follow their j: after each sub-step every lane
-// takes the sums of lane l + 1, which is the j it meets next.  No atomics, no
-// LDS writes and no barrier inside the loop.  The diagonal tile runs
-// s = 1..32 (s = 32 on half the lanes), which visits each pair i < j once.
-// Partial sums go to part[I][J] (i side) and part[J][I] (j side).
+// different j, and the j-side sums (Newton's third law) are added in LDS, one
+// slot per j, with no atomics and no barrier: the wavefront's LDS operations
+// complete in order, so a sub-step reads what the previous one wrote.  (Kept
+// in registers and rotated by one lane per sub-step instead, they cost twelve
+// DPP moves per pair on the vector ALU, which bounds this kernel.)  The
+// diagonal tile runs s = 1..32 (s = 32 on half the lanes), which visits each
+// pair i < j once.  Partial sums go to part[I][J] (i side) and part[J][I]
+// (j side).
 // MODE selects the starter: 0 plain; with a loaded network 1 plain with
 // domain statistics, 3 plain with harvest rows, 4 pairs that may lie in the
 // network's domain listed for k_deferred (which starts those in the domain
@@ -173,7 +165,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const double *V = S + 4 * (size_t)np;
     const double *XH = S + 7 * (size_t)np;
 
-    __shared__ double sj[7][TILE]; // x y z vx vy vz m of block J; later the j-side sums
+    __shared__ double sj[7][TILE];  // x y z vx vy vz m of block J (read only)
+    __shared__ double sjs[6][TILE]; // j-side sums, by slot of block J
     __shared__ unsigned shist[HIST ? 32 : 1];
 
     const int jg = J * TILE + lane;
@@ -189,13 +182,15 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const double xi[7] = {XH[ig], XH[np + ig], XH[2 * (size_t)np + ig], V[ig], V[np + ig],
                           V[2 * (size_t)np + ig], M[ig]};
     double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sjs[c][lane] = 0.0;
     if (HIST && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
     const double h = 0.5 * tau;
+    const double wgt_j = G * xi[6];
     const int nj = n - J * TILE; // valid j slots in this block
 
-    double jac[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; // sums of slot (lane + s) mod 64
     unsigned it_sum = 0, it_max = 0;          // per lane
     unsigned long long n_solve = 0, n_fb = 0; // per wave (ballot counts)
     GuessCount gc;                            // per wave
@@ -226,7 +221,9 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const bool collide = act && !(r0sq > 0.0);
         bool live = act && !collide;
         // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
-        kep::PairFlow f;
+        double d[6]; // increment of eq. (26) less the starting relative state, per unit mu
+        int iters;
+        bool conv, sg;
         if constexpr (MODE == 4) {
             // Pairs that may lie in the network's domain (a necessary condition
             // from the unreduced tau) are listed for k_deferred while the tile's
@@ -245,73 +242,75 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 room = room > total ? room - total : 0;
             }
         }
-        if constexpr (MODE == 0 || MODE == 4) {
-            f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
-                                 w2, live ? r0sq : 1.0, kp);
-        } else if constexpr (MODE == 1) {
-            f = kep::kepler_flow_domain(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
-                                        w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
-                                        net.tau2_hi, net.b_lo, net.e2_hi);
-            const bool dom = live && f.in_dom;
-            gc.dom += __popcll(__ballot(dom));
-            dom_it += dom ? (unsigned)f.iters : 0u;
-        } else { // harvest
-            kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
-            f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
-                                 w2, live ? r0sq : 1.0, kp, gp);
-            const bool dom = live && gp.in_dom;
-            gc.dom += __popcll(__ballot(dom));
-            dom_it += dom ? (unsigned)f.iters : 0u;
+        {
+            kep::PairFlow f;
+            if constexpr (MODE == 0 || MODE == 4) {
+                f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                                     w2, live ? r0sq : 1.0, kp);
+            } else if constexpr (MODE == 1) {
+                f = kep::kepler_flow_domain(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2,
+                                            w0, w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
+                                            net.tau2_hi, net.b_lo, net.e2_hi);
+                const bool dom = live && f.in_dom;
+                gc.dom += __popcll(__ballot(dom));
+                dom_it += dom ? (unsigned)f.iters : 0u;
+            } else { // harvest
+                kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
+                f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                                     w2, live ? r0sq : 1.0, kp, gp);
+                const bool dom = live && gp.in_dom;
+                gc.dom += __popcll(__ballot(dom));
+                dom_it += dom ? (unsigned)f.iters : 0u;
+            }
+            if (MODE == 3) { // the same relative state again, bitwise
+                asm volatile("" ::: "memory");
+                w0 = xi[3] - sj[3][q];
+                w1 = xi[4] - sj[4][q];
+                w2 = xi[5] - sj[5][q];
+                x0 = fma(-h, w0, xi[0] - sj[0][q]);
+                x1 = fma(-h, w1, xi[1] - sj[1][q]);
+                x2 = fma(-h, w2, xi[2] - sj[2][q]);
+            }
+            const double a = fma(-h, f.fdot, f.fm1);
+            const double b = fma(-h, f.gdm1, f.gmt);
+            d[0] = fma(a, x0, b * w0);
+            d[1] = fma(a, x1, b * w1);
+            d[2] = fma(a, x2, b * w2);
+            d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+            d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+            d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+            iters = f.iters;
+            conv = f.converged;
+            sg = f.safeguarded;
         }
-
-        if (MODE == 3) { // the same relative state again, bitwise
-            asm volatile("" ::: "memory");
-            w0 = xi[3] - sj[3][q];
-            w1 = xi[4] - sj[4][q];
-            w2 = xi[5] - sj[5][q];
-            x0 = fma(-h, w0, xi[0] - sj[0][q]);
-            x1 = fma(-h, w1, xi[1] - sj[1][q]);
-            x2 = fma(-h, w2, xi[2] - sj[2][q]);
-        }
-        // increments of eq. (26) minus the starting relative state
-        const double a = fma(-h, f.fdot, f.fm1);
-        const double b = fma(-h, f.gdm1, f.gmt);
-        const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
-                             fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
-                             fma(f.fdot, x2, f.gdm1 * w2)};
-        // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j)
-        const double inv = live ? kep::rcp_refined(msum) : 0.0;
-        const double wgt_i = mj * inv, wgt_j = mi * inv;
+        // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j),
+        // times mu = G (m_i + m_j) that the increments are divided by; lanes
+        // without a pair have zero increments (they solve tau = 0)
+        const double wgt_i = G * mj;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             ai[c] = fma(wgt_i, d[c], ai[c]);
-            jac[c] = from_next_lane(fma(-wgt_j, d[c], jac[c]));
+            sjs[c][q] = fma(-wgt_j, d[c], sjs[c][q]);
         }
-        it_sum += live ? f.iters : 0;
-        it_max = max(it_max, live ? (unsigned)f.iters : 0u);
+        it_sum += live ? iters : 0;
+        it_max = max(it_max, live ? (unsigned)iters : 0u);
         n_solve += __popcll(__ballot(live));
-        n_fb += __popcll(__ballot(live && f.safeguarded));
-        any_noconv = any_noconv || __ballot(live && !f.converged) != 0;
+        n_fb += __popcll(__ballot(live && sg));
+        any_noconv = any_noconv || __ballot(live && !conv) != 0;
         any_collide = any_collide || __ballot(collide) != 0;
-        if (HIST && live) atomicAdd(&shist[min(f.iters, 31)], 1u);
+        if (HIST && live) atomicAdd(&shist[min(iters, 31)], 1u);
     }
 
-    // After the last rotation lane l holds the sums of slot (l + s1) mod 64;
-    // put them in place through LDS.
-    __syncthreads();
-    const int slot = (lane + s1) & (TILE - 1);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sj[c][slot] = jac[c];
     __syncthreads();
     const size_t cs = TILE; // component stride inside a partial
     double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
     if (diag) {
-        for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + sj[c][lane];
+        for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + sjs[c][lane];
     } else {
         double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
         for (int c = 0; c < 6; ++c) {
             pij[c * cs] = ai[c];
-            pji[c * cs] = sj[c][lane];
+            pji[c * cs] = sjs[c][lane];
         }
     }
 
@@ -392,8 +391,8 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
         const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
                              fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
                              fma(f.fdot, x2, f.gdm1 * w2)};
-        const double inv = has ? kep::rcp_refined(msum) : 0.0;
-        const double wgt_i = mj * inv, wgt_j = mi * inv;
+        // the weights of k_pairs (the flow's coefficients are per unit mu)
+        const double wgt_i = G * mj, wgt_j = G * mi;
         __syncthreads(); // the previous item's readers of sc are done
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
