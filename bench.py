@@ -28,12 +28,13 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 # (add/sub/mul and the hardware reciprocal / reciprocal-square-root estimates
 # = 1, fma = 2) along the path almost every pair takes (one evaluation of the
 # Kepler equation in the cheapest tier, accepted with a first-order shift of
-# the G-functions): pair set-up and back-drift 19, Kepler set-up and starter
-# 47, the evaluation with its Halley step, convergence estimate and shift 78,
-# Lagrange coefficients 19, increments, weights and the two-sided sums 57;
-# every further evaluation (Laguerre step, general Stumpff series) 90.
-FLOPS_FIRST = 19 + 47 + 78 + 19 + 57
-FLOPS_PER_EXTRA_ITER = 90
+# the G-functions): pair set-up and back-drift 19, Kepler set-up, starter and
+# tier choice 43, the evaluation with its Halley step, convergence and error
+# estimates and shift 71, Lagrange coefficients 12, increments, weights and
+# the two-sided sums 47; every further evaluation (general Stumpff series,
+# Laguerre step and its tests) 92.
+FLOPS_FIRST = 19 + 43 + 71 + 12 + 47
+FLOPS_PER_EXTRA_ITER = 92
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
                   "paper_1402_3325_amd/csrc/common.hpp",

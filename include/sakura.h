@@ -55,10 +55,13 @@ enum { SAKURA_GUESS_ANALYTIC = 0, SAKURA_GUESS_LEARNED = 1 };
 
 typedef struct sakura sakura_t;
 
+#define SAKURA_MAX_ITER 1000 /* largest accepted sakura_opts.max_iter */
+
 typedef struct {
     int guess;          /* SAKURA_GUESS_ANALYTIC or SAKURA_GUESS_LEARNED */
     double kepler_rtol; /* relative tolerance on the Kepler root; 0 selects 2^-50 */
-    int max_iter;       /* Kepler iterations before ENOCONV; 0 selects 40 */
+    int max_iter;       /* Kepler iterations before ENOCONV; 0 selects 40; at most
+                           SAKURA_MAX_ITER (sakura_create fails with EINVAL above) */
     int histogram;      /* nonzero: fill sakura_stats.hist (one LDS atomic per pair) */
 } sakura_opts;
 

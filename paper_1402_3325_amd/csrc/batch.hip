@@ -114,7 +114,7 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                 const bool live = act && !collide;
                 kep::PairFlow f;
                 if constexpr (MODE == 0) {
-                    f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
+                    f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
                                          w1, w2, live ? r0sq : 1.0, kp);
                 } else {
                     double s_net = __builtin_nan("");
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                                                      w0, w1, w2, r0sq);
                     }
                     kep::NetGuess<MODE> gp(net, (int)p, (int)(off + ql), s_net);
-                    f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0,
+                    f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
                                          w1, w2, live ? r0sq : 1.0, kp, gp);
                     if (live && gp.in_dom) {
                         ++dom_n;

@@ -531,4 +531,14 @@ SAKURA_HD __attribute__((noinline)) PairFlow kepler_flow(double tau, double mu, 
     return kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
 }
 
+// Outcome of one pair's search packed for cheap accumulation: evaluations in
+// bits 16-31, a safeguarded step in bit 8, no convergence in bit 0.  Sums of
+// up to 64 of them keep the fields apart while every count of evaluations
+// stays below 1024 (a limit on KeplerParams::max_iter), and the maximum of
+// them carries the largest count of evaluations.
+SAKURA_HD inline unsigned pack_info(int iters, bool converged, bool safeguarded)
+{
+    return ((unsigned)iters << 16) | (safeguarded ? 0x100u : 0u) | (converged ? 0u : 1u);
+}
+
 } // namespace kep

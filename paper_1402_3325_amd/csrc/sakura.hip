@@ -191,12 +191,15 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const double wgt_j = G * xi[6];
     const int nj = n - J * TILE; // valid j slots in this block
 
-    unsigned it_sum = 0, it_max = 0;          // per lane
-    unsigned long long n_solve = 0, n_fb = 0; // per wave (ballot counts)
-    GuessCount gc;                            // per wave
-    unsigned dom_it = 0;                      // per lane
-    int room = kep::DEFER_CAP;                // MODE 4: list slots left
-    bool any_noconv = false, any_collide = false;
+    // Every lane solves a pair in every sub-step (lanes without one solve
+    // tau = 0: one evaluation, converged, never safeguarded), so the outcomes
+    // are summed over all lanes and the trivial ones taken off at the end.
+    unsigned info_sum = 0, info_max = 0; // per lane: sum and maximum of kep::pack_info
+    unsigned long long n_solve = 0;      // per wave (ballot count)
+    GuessCount gc;                       // per wave
+    unsigned dom_it = 0;                 // per lane
+    int room = kep::DEFER_CAP;           // MODE 4: list slots left
+    bool any_collide = false;
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
@@ -220,10 +223,10 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
         bool live = act && !collide;
-        // lanes without a pair solve a trivial problem (tau = 0, mu = 0, |x0| = 1)
+        // lanes without a pair solve a trivial problem (tau = 0, |x0| = 1; any
+        // finite mu): the starter is s = 0, where t(s) = 0 holds at once
         double d[6]; // increment of eq. (26) less the starting relative state, per unit mu
-        int iters;
-        bool conv, sg;
+        unsigned info;
         if constexpr (MODE == 4) {
             // Pairs that may lie in the network's domain (a necessary condition
             // from the unreduced tau) are listed for k_deferred while the tile's
@@ -245,10 +248,10 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         {
             kep::PairFlow f;
             if constexpr (MODE == 0 || MODE == 4) {
-                f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
                                      w2, live ? r0sq : 1.0, kp);
             } else if constexpr (MODE == 1) {
-                f = kep::kepler_flow_domain(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2,
+                f = kep::kepler_flow_domain(live ? tau : 0.0, G * msum, x0, x1, x2,
                                             w0, w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
                                             net.tau2_hi, net.b_lo, net.e2_hi);
                 const bool dom = live && f.in_dom;
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 dom_it += dom ? (unsigned)f.iters : 0u;
             } else { // harvest
                 kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
-                f = kep::kepler_flow(live ? tau : 0.0, live ? G * msum : 0.0, x0, x1, x2, w0, w1,
+                f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
                                      w2, live ? r0sq : 1.0, kp, gp);
                 const bool dom = live && gp.in_dom;
                 gc.dom += __popcll(__ballot(dom));
@@ -279,9 +282,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             d[3] = fma(f.fdot, x0, f.gdm1 * w0);
             d[4] = fma(f.fdot, x1, f.gdm1 * w1);
             d[5] = fma(f.fdot, x2, f.gdm1 * w2);
-            iters = f.iters;
-            conv = f.converged;
-            sg = f.safeguarded;
+            info = kep::pack_info(f.iters, f.converged, f.safeguarded);
         }
         // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j),
         // times mu = G (m_i + m_j) that the increments are divided by; lanes
@@ -292,13 +293,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             ai[c] = fma(wgt_i, d[c], ai[c]);
             sjs[c][q] = fma(-wgt_j, d[c], sjs[c][q]);
         }
-        it_sum += live ? iters : 0;
-        it_max = max(it_max, live ? (unsigned)iters : 0u);
-        n_solve += __popcll(__ballot(live));
-        n_fb += __popcll(__ballot(live && sg));
-        any_noconv = any_noconv || __ballot(live && !conv) != 0;
-        any_collide = any_collide || __ballot(collide) != 0;
-        if (HIST && live) atomicAdd(&shist[min(iters, 31)], 1u);
+        info_sum += info;
+        info_max = max(info_max, info);
+        n_solve += __popcll(__builtin_amdgcn_ballot_w64(live));
+        any_collide = any_collide || __builtin_amdgcn_ballot_w64(collide) != 0;
+        if (HIST && live) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
     }
 
     __syncthreads();
@@ -314,8 +313,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         }
     }
 
-    it_sum = wave_sum(it_sum);
-    it_max = wave_max(it_max);
+    const unsigned trivial = (unsigned)(TILE * (s1 - s0)) - (unsigned)n_solve;
+    const unsigned it_sum = wave_sum(info_sum >> 16) - trivial;
+    const unsigned it_max = n_solve ? wave_max(info_max >> 16) : 0u;
+    const unsigned n_fb = wave_sum((info_sum >> 8) & 0xffu);
+    const bool any_noconv = wave_sum(info_sum & 0xffu) != 0;
     if (MODE != 0) gc.dom_iters = wave_sum(dom_it);
     const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
     if (lane == 0) {
@@ -663,7 +665,8 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     if (opts) h->opts = *opts;
     if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = 0x1p-50;
     if (h->opts.max_iter <= 0) h->opts.max_iter = 40;
-    if (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED) {
+    if (h->opts.max_iter > SAKURA_MAX_ITER ||
+        (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED)) {
         delete h;
         return SAKURA_EINVAL;
     }

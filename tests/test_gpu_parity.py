@@ -210,3 +210,40 @@ def test_energy_matches_oracle(torch, lib, oracle):
         assert abs(eg["K"] - eo["K"]) <= 1e-14 * eo["K"]
         for key in ("P", "L", "Rcm"):
             assert np.max(np.abs(np.array(eg[key]) - eo[key])) <= 1e-14 * (1 + np.abs(eo[key]).max())
+
+
+def test_counters_agree_with_histogram(torch):
+    """The pair kernel's per-lane packed counters (evaluations, safeguarded
+    steps, solved pairs) against the exact number of pairs and the per-pair
+    histogram, which the kernel counts independently in LDS."""
+    from paper_1402_3325_amd.sakura import Sakura
+    m, r, v, tau = workloads.cluster()  # N = 16384: some pairs need two or more evaluations
+    m2, r2, v2, _ = workloads.plummer(333, rng=np.random.default_rng(8))
+    m2 = m2.copy()
+    m2[::7] = 0.0  # pairs of two massless particles are not solved
+    hh, hp = Sakura(0, histogram=True), Sakura(0)
+    try:
+        for mm, rr, vv, dt in ((m, r, v, tau), (m2, r2, v2, 0.05)):
+            n, nz = len(mm), int(np.sum(mm == 0.0))
+            pairs = n * (n - 1) // 2 - nz * (nz - 1) // 2
+            st_h = hh.evolve(*_dev(torch, mm, rr, vv), dt, 1, stats=True)
+            st_p = hp.evolve(*_dev(torch, mm, rr, vv), dt, 1, stats=True)
+            hist = np.array(st_h["hist"], dtype=np.int64)
+            assert hist[31] == 0 and hist[0] == 0
+            assert st_h["pair_solves"] == st_p["pair_solves"] == pairs == hist.sum()
+            assert st_h["iters_total"] == st_p["iters_total"] == int(np.sum(np.arange(32) * hist))
+            assert st_h["iters_max"] == st_p["iters_max"] == int(np.nonzero(hist)[0].max())
+            assert st_h["fallbacks"] == st_p["fallbacks"]
+            assert st_p["iters_total"] > st_p["pair_solves"]  # not only one-evaluation pairs
+    finally:
+        hh.close()
+        hp.close()
+
+
+def test_max_iter_limit(torch):
+    from paper_1402_3325_amd.sakura import Sakura, SakuraError, EINVAL
+    with pytest.raises(SakuraError) as e:
+        Sakura(0, max_iter=1001)
+    assert e.value.code == EINVAL
+    h = Sakura(0, max_iter=1000)
+    h.close()
