@@ -227,18 +227,31 @@ SAKURA_HD inline void taylor_shift3(KepIter &st, const KepEval &e, double d, dou
 // taking lane, to second order when |ds| <= 2^-18 |s - ds| (the dropped terms
 // are then below 3 (ds/s)^2 resp. (ds/s)^3, i.e. below 2^-54 of each
 // function), else, as in the other tiers, to third order.
+//
+// With EASY (tier 2, every lane of the wavefront started by the plain starter
+// with corrections |corr1| + |corr2| = c <= 2^-9, and tol >= 2^-52) the error
+// bound needs no evaluation: at such a starter |t2 s / r| <= 8.2 c and
+// |t3| s^2 / r <= 6.2 c (t2 s ~ eta s + zeta s^2, whose terms the corrections
+// bound through 2 |corr1| and 6 |A3 u^2| <= 6 (c + 2 c^2)), so
+// C s^2 <= 6.2 c + 67 c^2 <= 0.0124, and a step with |ds| <= 2^-16 |s - ds|
+// leaves an error below 2^-48 C s^2 |s - ds| <= tol |s - ds| / 4.
 template <int TIER>
 SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double zeta, double r0,
-                                  double t, double tol)
+                                  double t, double tol, bool easy)
 {
     const double s = st.s;
     const KepEval e = kepler_eval<TIER>(s, beta, eta, zeta, r0, t);
     const double ds = laguerre_step<TIER == 2>(e);
     const double ads = fabs(ds);
     const double sn = s - ds;
-    const bool done = ads <= tol * fabs(s) || e.F == 0.0 ||
-                      step_accepted(e, ds, sn, beta, eta, zeta, tol);
-    const double d = -ds, asn = fabs(sn);
+    const double asn = fabs(sn);
+    bool done;
+    if (TIER == 2 && easy)
+        done = ads <= tol * fabs(s) || e.F == 0.0 || ads <= 0x1p-16 * asn;
+    else
+        done = ads <= tol * fabs(s) || e.F == 0.0 ||
+               step_accepted(e, ds, sn, beta, eta, zeta, tol);
+    const double d = -ds;
     double G3 = fma(d, e.G2, e.G3);
     double G2 = fma(d, e.G1, e.G2);
     double G1 = fma(d, e.G0, e.G1);
@@ -353,7 +366,8 @@ SAKURA_HD inline double reduce_time(double tau, double mu, double beta, double &
 // A starter beyond |s| <= s_half or of the wrong sign is replaced by u,
 // clamped to that bound.
 SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0inv, double eta,
-                                      double zeta, double beta, double mu, double s_half)
+                                      double zeta, double beta, double mu, double s_half,
+                                      double &csum_out)
 {
     const double p = eta * r0inv;                 // 2 A2
     const double A3 = (1.0 / 6.0) * (zeta * r0inv);
@@ -361,6 +375,7 @@ SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0in
     const double uu = u * u;
     const double corr2 = fma(0.5 * p, p, -A3) * uu; // (2 A2^2 - A3) u^2
     const double csum = fabs(corr1) + fabs(corr2);
+    csum_out = csum;
     double corr = corr1 + corr2;
     if (csum > 0x1p-9) {
         const double A2 = 0.5 * p;
@@ -420,16 +435,16 @@ struct NoGuess {
 // general tier.
 SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double zeta, double r0,
                                    double t, double u, double s_half, const KeplerParams &kp,
-                                   int &it)
+                                   bool easy, int &it)
 {
     const double z0 = fabs(beta * st.s * st.s);
     int res;
     if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
-        res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol, easy);
     else if (SAKURA_WAVE_ALL(z0 <= 0x1p-10))
-        res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol, false);
     else
-        res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol);
+        res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol, false);
     it = 1;
     if (res == 0) {
         initial_bracket(t, u, beta, eta, s_half, st.lo, st.hi);
@@ -471,7 +486,8 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
     double s_half, tshift_mu;
     const double t = reduce_time(tau, mu, beta, s_half, tshift_mu);
     const double u = t * r0inv;
-    double s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half);
+    double csum;
+    double s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum);
     bool replaced = false;
     if (Guess::active) {
         double lo, hi;
@@ -489,16 +505,18 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
         replaced = how == START_REPLACED;
     }
 
+    // the simplified acceptance of kepler_first (uniform over the wavefront)
+    const bool easy = kp.tol >= 0x1p-52 && SAKURA_WAVE_ALL(csum <= 0x1p-9 && !replaced);
     KepIter st{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
     int it = 0;
-    int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, it);
+    int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, easy, it);
     bool restarted = false;
     if (Guess::active && res == 0 && replaced) {
         restarted = true;
-        s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half);
+        s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum);
         st = KepIter{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
         int it2 = 0;
-        res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, it2);
+        res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, false, it2);
         it += it2;
     }
     PairFlow out;
