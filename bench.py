@@ -28,12 +28,13 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 # (add/sub/mul and the hardware reciprocal / reciprocal-square-root estimates
 # = 1, fma = 2) along the path almost every pair takes (one evaluation of the
 # Kepler equation in the cheapest tier, accepted with a first-order shift of
-# the G-functions): pair set-up and back-drift 19, Kepler set-up, starter and
-# tier choice 43, the evaluation with its Halley step, convergence and error
-# estimates and shift 71, Lagrange coefficients 12, increments, weights and
-# the two-sided sums 47; every further evaluation (general Stumpff series,
+# the G-functions, its error bound implied by the starter's small
+# corrections): pair set-up and back-drift 19, Kepler set-up, starter and tier
+# choice 42, the evaluation with its Halley step, convergence and acceptance
+# tests and shift 57, Lagrange coefficients 12, increments, weights and the
+# two-sided sums 47; every further evaluation (general Stumpff series,
 # Laguerre step and its tests) 92.
-FLOPS_FIRST = 19 + 43 + 71 + 12 + 47
+FLOPS_FIRST = 19 + 42 + 57 + 12 + 47
 FLOPS_PER_EXTRA_ITER = 92
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
@@ -54,16 +55,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per pair-kernel launch from the committed rocprofv3 counters,
-    or None when the kernel sources changed since they were taken."""
+def measured_profile():
+    """The committed rocprofv3 counter record of the pair kernel (HBM bytes
+    per launch, clock, hardware FP64 operations per pair), or None when the
+    kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec["bytes_per_launch"]
+    return rec
 
 
 def flops_per_pair(mean_iters):
@@ -310,7 +312,8 @@ def main():
     pair_ms = st["pair_kernel_ms"] / max(st["pair_launches"], 1)
     fl = flops_per_pair(k_mean) * pairs
     achieved = fl / (pair_ms * 1e-3) / 1e12
-    traffic = measured_traffic()
+    prof = measured_profile()
+    traffic = prof["bytes_per_launch"] if prof else None
 
     out = {
         "metric": METRIC,
@@ -331,6 +334,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic},
+        # the same roofline at the clock the counters measured during the
+        # kernel, and the FP64 work the hardware counted (null when the
+        # committed counters predate the kernel sources)
+        "roofline_at_measured_clock": ({
+            "clock_ghz": prof["clock_ghz"],
+            "peak": PEAK_FP64_TFLOPS * prof["clock_ghz"] / 2.4,
+            "frac": achieved / (PEAK_FP64_TFLOPS * prof["clock_ghz"] / 2.4),
+            "hw_fp64_flops_per_pair": prof["hw_fp64_flops_per_pair"],
+            "valu_busy": prof["valu_busy"]} if prof else None),
         "pair_kernel_ms": pair_ms,
         "call_ms_events": st["call_ms"],
         "mean_kepler_iters": k_mean,

@@ -226,6 +226,19 @@ SAKURA_HD inline bool pair_may_qualify(const GuessNet &g, double tau, double mu,
     const double t2 = tau * tau;
     return mu > 0.0 && t2 * t2 * (mu * mu) >= g.tau4_lo * (r0sq * r0sq * r0sq);
 }
+// The same test with tau^4 / tau_lo^4 formed once per launch (q4 from
+// may_qualify_scale; zero without a model) and widened by 2^-40 so that its
+// rounding never drops a pair the test above keeps: mu^2 q4 >= r0^6, with no
+// branch (mu = 0 or q4 = 0 fails it for every r0 > 0).
+SAKURA_HD inline double may_qualify_scale(const GuessNet &g, double tau)
+{
+    const double t2 = tau * tau;
+    return t2 * t2 / g.tau4_lo * (1.0 + 0x1p-40);
+}
+SAKURA_HD inline bool pair_may_qualify_q(double q4, double mu, double r0sq)
+{
+    return mu * mu * q4 >= r0sq * r0sq * r0sq;
+}
 
 #ifndef SAKURA_HOST_ONLY
 // The network's starter for a pair, or NaN outside the domain: the setup of

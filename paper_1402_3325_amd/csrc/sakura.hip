@@ -189,6 +189,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const bool valid_i = ig < n;
     const double h = 0.5 * tau;
     const double wgt_j = G * xi[6];
+    const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
     const int nj = n - J * TILE; // valid j slots in this block
 
     // Every lane solves a pair in every sub-step (lanes without one solve
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             // Pairs that may lie in the network's domain (a necessary condition
             // from the unreduced tau) are listed for k_deferred while the tile's
             // list has room, and skipped here; the rest take the plain solve.
-            const bool cand = live && kep::pair_may_qualify(net, tau, G * msum, r0sq);
-            const unsigned long long mask = __ballot(cand);
+            const bool cand = live & kep::pair_may_qualify_q(q4, G * msum, r0sq);
+            const unsigned long long mask = __builtin_amdgcn_ballot_w64(cand);
             if (mask) {
                 const unsigned long long below =
                     lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
