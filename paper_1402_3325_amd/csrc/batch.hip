@@ -114,8 +114,15 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                 const bool live = act && !collide;
                 kep::PairFlow f;
                 if constexpr (MODE == 0) {
-                    f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
-                                         w1, w2, live ? r0sq : 1.0, kp);
+                    const kep::PairCoef c = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1,
+                                                             x2, w0, w1, w2, live ? r0sq : 1.0, kp);
+                    f.fm1 = c.fm1;
+                    f.gmt = c.gmt;
+                    f.fdot = c.fdot;
+                    f.gdm1 = c.gdm1;
+                    f.iters = c.iters;
+                    f.converged = !(c.status & 1u);
+                    f.safeguarded = (c.status & 0x100u) != 0;
                 } else {
                     double s_net = __builtin_nan("");
                     if (MODE == 2) {

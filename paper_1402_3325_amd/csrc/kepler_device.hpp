@@ -540,13 +540,22 @@ SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x
 // register allocation of the pair loop from that of the solver, which
 // measured about 3 % faster in the tile kernel than the inlined form (which
 // keeps more state live across the solve and spills inside the loop).
-SAKURA_HD __attribute__((noinline)) PairFlow kepler_flow(double tau, double mu, double x0,
+// Its result: the coefficients of PairFlow, the evaluations, and the status
+// bits of pack_info (0x100 safeguarded, 1 not converged).
+struct PairCoef {
+    double fm1, gmt, fdot, gdm1;
+    int iters;
+    unsigned status;
+};
+SAKURA_HD __attribute__((noinline)) PairCoef kepler_flow(double tau, double mu, double x0,
                                                          double x1, double x2, double w0,
                                                          double w1, double w2, double r0sq,
                                                          const KeplerParams &kp)
 {
     NoGuess g;
-    return kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    return PairCoef{f.fm1, f.gmt, f.fdot, f.gdm1, f.iters,
+                    (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u)};
 }
 
 // Outcome of one pair's search packed for cheap accumulation: evaluations in

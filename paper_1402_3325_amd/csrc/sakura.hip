@@ -246,12 +246,21 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 room = room > total ? room - total : 0;
             }
         }
-        {
+        if constexpr (MODE == 0 || MODE == 4) {
+            const kep::PairCoef f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
+                                                     w1, w2, live ? r0sq : 1.0, kp);
+            const double a = fma(-h, f.fdot, f.fm1);
+            const double b = fma(-h, f.gdm1, f.gmt);
+            d[0] = fma(a, x0, b * w0);
+            d[1] = fma(a, x1, b * w1);
+            d[2] = fma(a, x2, b * w2);
+            d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+            d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+            d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+            info = ((unsigned)f.iters << 16) | f.status;
+        } else {
             kep::PairFlow f;
-            if constexpr (MODE == 0 || MODE == 4) {
-                f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
-                                     w2, live ? r0sq : 1.0, kp);
-            } else if constexpr (MODE == 1) {
+            if constexpr (MODE == 1) {
                 f = kep::kepler_flow_domain(live ? tau : 0.0, G * msum, x0, x1, x2,
                                             w0, w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
                                             net.tau2_hi, net.b_lo, net.e2_hi);
