@@ -35,6 +35,9 @@ struct KeplerParams {
     double tol;   // relative convergence tolerance on s
     int max_iter; // Laguerre iterations before the pair is declared unconverged
 };
+// The library's defaults (sakura_opts with zeros).
+constexpr double DEFAULT_TOL = 0x1p-50;
+constexpr int DEFAULT_MAX_ITER = 40;
 
 // c2(z), c3(z) from sum_m (-z)^m / (2m+k)! for |z| <= 1/4 (seven terms leave a
 // truncation below 0.05 ulp), extended to any z by c2(4z) = c1(z)^2 / 2 and
@@ -472,7 +475,9 @@ SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double 
 // With a starter policy that replaced the plain starter, a search that fails
 // to converge is started again from the plain starter (PairFlow::restarted).
 template <class Guess>
-SAKURA_HD inline PairFlow kepler_flow(double tau, double mu, double x0, double x1, double x2,
+SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau, double mu,
+                                                                     double x0, double x1,
+                                                                     double x2,
                                       double w0, double w1, double w2, double r0sq,
                                       const KeplerParams &kp, Guess &guess)
 {
@@ -552,6 +557,20 @@ SAKURA_HD __attribute__((noinline)) PairCoef kepler_flow(double tau, double mu, 
                                                          double w1, double w2, double r0sq,
                                                          const KeplerParams &kp)
 {
+    NoGuess g;
+    const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    return PairCoef{f.fm1, f.gmt, f.fdot, f.gdm1, f.iters,
+                    (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u)};
+}
+// The same with the default parameters built in: three fewer argument
+// registers to fill per call, and the tolerance folded into the tests.
+SAKURA_HD __attribute__((noinline)) PairCoef kepler_flow_default(double tau, double mu,
+                                                                 double x0, double x1,
+                                                                 double x2, double w0,
+                                                                 double w1, double w2,
+                                                                 double r0sq)
+{
+    constexpr KeplerParams kp{DEFAULT_TOL, DEFAULT_MAX_ITER};
     NoGuess g;
     const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
     return PairCoef{f.fm1, f.gmt, f.fdot, f.gdm1, f.iters,

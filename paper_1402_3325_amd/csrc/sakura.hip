@@ -147,7 +147,7 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 // domain statistics, 3 plain with harvest rows, 4 pairs that may lie in the
 // network's domain listed for k_deferred (which starts those in the domain
 // from the network) and the rest solved plainly.
-template <bool HIST, int MODE>
+template <bool HIST, int MODE, bool DEFKP = false>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double G, const double *__restrict__ S,
                                                 double *__restrict__ part,
@@ -247,8 +247,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             }
         }
         if constexpr (MODE == 0 || MODE == 4) {
-            const kep::PairCoef f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
-                                                     w1, w2, live ? r0sq : 1.0, kp);
+            const kep::PairCoef f =
+                DEFKP ? kep::kepler_flow_default(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
+                                                 w2, live ? r0sq : 1.0)
+                      : kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2,
+                                         live ? r0sq : 1.0, kp);
             const double a = fma(-h, f.fdot, f.fm1);
             const double b = fma(-h, f.gdm1, f.gmt);
             d[0] = fma(a, x0, b * w0);
@@ -624,12 +627,19 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
                     double G, const double *S, double *part, DevCounters *cnt, SlotStats *slots,
                     kep::KeplerParams kp, long long step, const kep::GuessNet &net)
 {
+    // the plain solve with the default parameters built in, where they apply
+    const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
     switch (mode) {
     case 1:
         k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
         break;
     case 2: // the network's starter: pairs of its domain go through k_deferred
-        k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        if (defkp)
+            k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
+                                                            step, net);
+        else
+            k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
+                                                      step, net);
         k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, G, S, part, cnt, slots, kp,
                                                           step, net);
         break;
@@ -637,7 +647,12 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
         k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
         break;
     default:
-        k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        if (defkp)
+            k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
+                                                            step, net);
+        else
+            k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
+                                                      step, net);
     }
 }
 
@@ -673,8 +688,8 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     sakura_t *h = new sakura();
     h->device = device;
     if (opts) h->opts = *opts;
-    if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = 0x1p-50;
-    if (h->opts.max_iter <= 0) h->opts.max_iter = 40;
+    if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = kep::DEFAULT_TOL;
+    if (h->opts.max_iter <= 0) h->opts.max_iter = kep::DEFAULT_MAX_ITER;
     if (h->opts.max_iter > SAKURA_MAX_ITER ||
         (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED)) {
         delete h;

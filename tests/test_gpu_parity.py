@@ -247,3 +247,18 @@ def test_max_iter_limit(torch):
     assert e.value.code == EINVAL
     h = Sakura(0, max_iter=1000)
     h.close()
+
+
+def test_default_parameters_kernel_matches_general(torch, lib):
+    """The tile kernel built for the default solver parameters and the general
+    one (any other max_iter) do the same arithmetic: identical results."""
+    from paper_1402_3325_amd.sakura import Sakura
+    m, r, v, tau = workloads.plummer(4096, rng=np.random.default_rng(5))
+    hg = Sakura(0, max_iter=41)
+    try:
+        ra, va, sa = gpu_step(torch, lib, m, r, v, tau, nsteps=2, stats=True)
+        rb, vb, sb = gpu_step(torch, hg, m, r, v, tau, nsteps=2, stats=True)
+    finally:
+        hg.close()
+    assert np.array_equal(ra, rb) and np.array_equal(va, vb)
+    assert sa["iters_total"] == sb["iters_total"] and sa["pair_solves"] == sb["pair_solves"]
