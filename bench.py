@@ -232,6 +232,47 @@ def learned(torch, m, r, v, tau, steps, warmup, harvest_steps):
     return out
 
 
+def accuracy_study(torch):
+    """The paper's accuracy studies on the GPU (synthetic inputs): the relative
+    energy error after one N-body time unit of the 128-star Plummer sphere
+    around a black hole of q star masses, for tau = 1e-3, 1e-4, 1e-5 (Sec. 3.2),
+    and after one outer period of two circular binaries on a circular outer
+    orbit with a_out/a_in = 10, 100, 1000 (Sec. 3.1)."""
+    from paper_1402_3325_amd import workloads
+    from paper_1402_3325_amd.sakura import Sakura
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    h = Sakura(0)
+    t0 = time.perf_counter()
+
+    def rel_de(m, r, v, tau, nsteps):
+        mt, rt, vt = dev(m), dev(r), dev(v)
+        e0 = h.energy(mt, rt, vt)["E"]
+        h.evolve(mt, rt, vt, tau, nsteps)
+        e1 = h.energy(mt, rt, vt)["E"]
+        return abs((e1 - e0) / e0)
+
+    pbh = {}
+    for q in (1.0, 1e1, 1e2, 1e3, 1e6, 1e9, 1e12):
+        m, r, v = workloads.plummer_bh(q=q)
+        pbh[f"{q:.0e}"] = {f"{tau:.0e}": rel_de(m, r, v, tau, int(round(1.0 / tau)))
+                           for tau in (1e-3, 1e-4, 1e-5)}
+    h4 = {}
+    for ratio in (10.0, 100.0, 1000.0):
+        m, r, v, P = workloads.hierarchical4(ratio)
+        h4[f"{ratio:.0f}"] = {f"{tau:.0e}": rel_de(m, r, v, tau, int(round(P / tau)))
+                              for tau in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5)}
+    h.close()
+    return {"study": "relative energy error |dE/E|, G = 1",
+            "plummer_bh": {"workload": "128 equal-mass Plummer stars + central black hole of "
+                                       "q star masses, virial, total mass 1; 1 time unit",
+                           "dE_over_E": pbh},
+            "hierarchical4": {"workload": "two circular binaries (masses 1/4, a_in = "
+                                          "1/ratio) on a circular outer orbit a_out = 1; "
+                                          "one outer period",
+                              "dE_over_E": h4},
+            "seconds": time.perf_counter() - t0}
+
+
 def cpu_baseline(m, r, v, tau, budget_s=15.0):
     """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
     a bounded sample: rows of one step of the same workload."""
@@ -266,6 +307,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--harvest-steps", type=int, default=2000)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="only run the accuracy studies (energy error vs mass ratio and "
+                         "binary hierarchy) and print their JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (x4), to scale "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -287,6 +331,10 @@ def main():
     import torch
     from paper_1402_3325_amd import workloads
     from paper_1402_3325_amd.sakura import Sakura
+
+    if args.accuracy:
+        print(json.dumps(accuracy_study(torch)), flush=True)
+        return
 
     m, r, v, tau, _ = workloads.config(2)
     n = len(m)

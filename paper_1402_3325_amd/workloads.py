@@ -20,6 +20,10 @@ Workloads (G = 1 throughout):
   primordial binaries, the regimes the abstract and Sec. 3.2 single out.
 * ``ensemble``   -- many independent planetary systems of uneven size in CSR
   layout.
+* ``plummer_bh`` -- a 128-star Plummer sphere around a black hole of q star
+  masses, q = 1 .. 1e12: the mass-ratio accuracy study of Sec. 3.2.
+* ``hierarchical4`` -- two circular binaries on a circular outer orbit,
+  a_out/a_in = 10 .. 1000: the hierarchical accuracy test of Sec. 3.1.
 * ``test_particles`` -- one massive body plus massless particles (each follows an
   exact two-body orbit under the method).
 * ``kepler_cases``   -- random two-body states (elliptic, hyperbolic,
@@ -211,6 +215,53 @@ def cluster(n_stars=16383, binary_fraction=0.1, m_bh=0.01, rng=None):
     m, r, v = m[perm], r[perm], v[perm]
     r, v = _to_com_frame(m, r, v)
     return m, r, v, 1.0 / 2048.0
+
+
+def plummer_bh(n_stars=128, q=1.0e6, rng=None):
+    """Plummer sphere of n_stars equal-mass stars around a central black hole
+    of q star masses (the mass-ratio study of Sec. 3.2): G = 1, total mass 1,
+    the stars at the Henon length scale of a Plummer sphere, centre of mass at
+    rest, and the velocities scaled to virial equilibrium, 2K = |U| (so E =
+    U/2; the length scale is not stretched to E = -1/4, which for large q
+    would shrink the system until the stars' orbits about the black hole were
+    far shorter than any step).  Returns m, r, v with the black hole at index
+    0 (q = 1: one more star).  The same seed gives the same stellar positions
+    and velocity directions for every q."""
+    if rng is None:
+        rng = rng_for(5)
+    r, v = _plummer_raw(n_stars, rng)
+    ms = 1.0 / (n_stars + q)
+    m = np.concatenate([[q * ms], np.full(n_stars, ms)])
+    r = np.concatenate([np.zeros((1, 3)), r * (3.0 * np.pi / 16.0)])
+    v = np.concatenate([np.zeros((1, 3)), v])
+    r, v = _to_com_frame(m, r, v)
+    U = potential_energy(m, r)
+    K = 0.5 * np.sum(m * np.einsum("ij,ij->i", v, v))
+    v = v * np.sqrt(-0.5 * U / K)
+    return m, r, v
+
+
+def hierarchical4(ratio=100.0, rng=None):
+    """Two equal circular binaries (masses 1/4, separation a_in = 1/ratio) on
+    a circular outer orbit of separation 1 (the hierarchical test of Sec. 3.1;
+    total mass 1, G = 1, so the outer period is 2 pi).  Orbits are coplanar and
+    prograde with random phases; centre of mass at rest.  Returns m, r, v and
+    the outer period."""
+    if rng is None:
+        rng = rng_for(6)
+    a_in = 1.0 / ratio
+    xo, wo = elements_to_state(1.0, 1.0, 0.0, 0.0, 0.0, 0.0, rng.uniform(0.0, 2.0 * np.pi))
+    ph = rng.uniform(0.0, 2.0 * np.pi, 2)
+    xi, wi = elements_to_state(0.5, a_in, 0.0, 0.0, 0.0, 0.0, ph)
+    m = np.full(4, 0.25)
+    cm = [0.5 * xo, -0.5 * xo]
+    cv = [0.5 * wo, -0.5 * wo]
+    r = np.stack([cm[0] + 0.5 * xi[0], cm[0] - 0.5 * xi[0],
+                  cm[1] + 0.5 * xi[1], cm[1] - 0.5 * xi[1]])
+    v = np.stack([cv[0] + 0.5 * wi[0], cv[0] - 0.5 * wi[0],
+                  cv[1] + 0.5 * wi[1], cv[1] - 0.5 * wi[1]])
+    r, v = _to_com_frame(m, r, v)
+    return m, r, v, 2.0 * np.pi
 
 
 def ensemble(n_sys=4096, n_min=3, n_max=64, seed=SEED_BASE + 4):
