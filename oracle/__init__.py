@@ -16,6 +16,10 @@ SOLVER_KEPLER = 0
 SOLVER_KEPLER_LITERAL = 1
 SOLVER_DKD = 2
 
+SCHEME_PSI = 0
+SCHEME_UNMERGED = 1
+SCHEME_TRIPLE_JUMP = 2
+
 ERRORS = {0: "ok", -1: "EINVAL", -2: "ENONFINITE", -3: "ECOLLIDE", -4: "ENOCONV"}
 
 
@@ -51,6 +55,11 @@ def lib():
                                      ctypes.c_double, ctypes.c_int64, _I64, _D, _D]
         L.sref_evolve.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
                                   ctypes.c_int64, ctypes.c_double, ctypes.c_int]
+        L.sref_pair_map.argtypes = [ctypes.c_double] * 6 + [_D] * 6
+        L.sref_w_stage.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.sref_evolve_scheme.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                         ctypes.c_int64, ctypes.c_double, ctypes.c_int]
         L.sref_energy.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]
         L.sref_num_threads.restype = ctypes.c_int
         L.sref_mlp_forward.argtypes = [_D, ctypes.c_int64, _D, _D]
@@ -130,6 +139,45 @@ def evolve(m, r, v, tau, nsteps, G=1.0, solver=SOLVER_KEPLER):
                            float(G), int(solver))
     if rc:
         raise OracleError(rc, "sref_evolve")
+    return r, v
+
+
+def pair_map(t, cb, ca, G, mi, mj, ri, vi, rj, vj):
+    """Relative increments of one pair under back-drift cb, Kepler flow t,
+    back-drift ca (eqs. 19a, 19b, 26 are special cases)."""
+    a = [_f64(x, (3,)).copy() for x in (ri, vi, rj, vj)]
+    dr = np.empty(3)
+    dv = np.empty(3)
+    rc = lib().sref_pair_map(float(t), float(cb), float(ca), float(G), float(mi), float(mj),
+                             _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]), _p(dr), _p(dv))
+    if rc:
+        raise OracleError(rc, "sref_pair_map")
+    return dr, dv
+
+
+def w_stage(m, r, v, t, cb, ca, G=1.0):
+    """One W stage (eq. 23 with the pair map (t, cb, ca)), no drifts."""
+    m = _f64(m)
+    n = m.shape[0]
+    r = _f64(r, (n, 3)).copy()
+    v = _f64(v, (n, 3)).copy()
+    rc = lib().sref_w_stage(n, _p(m), _p(r), _p(v), float(t), float(cb), float(ca), float(G))
+    if rc:
+        raise OracleError(rc, "sref_w_stage")
+    return r, v
+
+
+def evolve_scheme(m, r, v, tau, nsteps, scheme, G=1.0):
+    """nsteps steps of a composition scheme (SCHEME_PSI, SCHEME_UNMERGED,
+    SCHEME_TRIPLE_JUMP)."""
+    m = _f64(m)
+    n = m.shape[0]
+    r = _f64(r, (n, 3)).copy()
+    v = _f64(v, (n, 3)).copy()
+    rc = lib().sref_evolve_scheme(n, _p(m), _p(r), _p(v), float(tau), int(nsteps),
+                                  float(G), int(scheme))
+    if rc:
+        raise OracleError(rc, "sref_evolve_scheme")
     return r, v
 
 

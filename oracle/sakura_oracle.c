@@ -353,6 +353,35 @@ int sref_pair_increment(double tau, double G, double mi, double mj,
     return SREF_OK;
 }
 
+/* The general pair map behind eqs. (19a, 19b, 26): back-drift the relative
+ * position by cb (eq. 17), Kepler flow over t (eq. 18), back-drift by ca.
+ * With x0 = X - cb W and k = {f-1, g-t, fdot, gdot-1} of the flow:
+ *   X + dr = f x0 + g W - ca (fdot x0 + gdot W),   X = x0 + cb W,
+ * so dr = (f - 1 - ca fdot) x0 + (g - ca gdot - cb) W
+ *       = (k0 - ca k2) x0 + ((k1 - ca k3) + (t - ca - cb)) W,
+ *    dv = fdot x0 + (gdot - 1) W.                                            */
+int sref_pair_map(double t, double cb, double ca, double G, double mi, double mj,
+                  const double ri[3], const double vi[3], const double rj[3],
+                  const double vj[3], double dr[3], double dv[3])
+{
+    double X[3], W[3], x0[3];
+    for (int c = 0; c < 3; ++c) {
+        X[c] = ri[c] - rj[c];
+        W[c] = vi[c] - vj[c];
+        x0[c] = X[c] - W[c] * cb;
+    }
+    double x1[3], w1[3], k[4];
+    int rc = sref_kepler(t, G * (mi + mj), x0, W, x1, w1, k, NULL);
+    if (rc) return rc;
+    double a = k[0] - ca * k[2];
+    double b = (k[1] - ca * k[3]) + (t - ca - cb);
+    for (int c = 0; c < 3; ++c) {
+        dr[c] = a * x0[c] + b * W[c];
+        dv[c] = k[2] * x0[c] + k[3] * W[c];
+    }
+    return SREF_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Full step, eqs. (27a-d).                                                  */
 /* ------------------------------------------------------------------------ */
@@ -478,6 +507,133 @@ int sref_evolve(int64_t n, const double *m, double *r, double *v, double tau,
     if (nsteps < 0) return SREF_EINVAL;
     for (int64_t s = 0; s < nsteps; ++s) {
         int rc = sref_step(n, m, r, v, tau, G, solver);
+        if (rc) return rc;
+    }
+    return SREF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compositions of the step (Sec. 2.2): eq. (24) unmerged, and the triple    */
+/* jump of eq. (25).                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Row i of a W stage: the eq. (23) sums with the pair map (t, cb, ca), from
+ * the state (r, v) that every pair of the stage sees. */
+static int stage_row(int64_t n, const double *m, const double *r, const double *v,
+                     double t, double cb, double ca, double G, int64_t i, double rn[3],
+                     double vn[3])
+{
+    long double ar[3] = {0.0L, 0.0L, 0.0L}, av[3] = {0.0L, 0.0L, 0.0L};
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double mij = m[i] + m[j];
+        if (mij == 0.0) continue;
+        double w = m[j] / mij;
+        double dr[3], dv[3];
+        int rc = sref_pair_map(t, cb, ca, G, m[i], m[j], r + 3 * i, v + 3 * i, r + 3 * j,
+                               v + 3 * j, dr, dv);
+        if (rc) return rc;
+        for (int c = 0; c < 3; ++c) {
+            ar[c] += (long double)w * (long double)dr[c];
+            av[c] += (long double)w * (long double)dv[c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        rn[c] = (double)((long double)r[3 * i + c] + ar[c]);
+        vn[c] = (double)((long double)v[3 * i + c] + av[c]);
+    }
+    return SREF_OK;
+}
+
+int sref_w_stage(int64_t n, const double *m, double *r, double *v, double t, double cb,
+                 double ca, double G)
+{
+    int rc = check_args(n, m, r, v, t, G);
+    if (rc) return rc;
+    if (!isfinite(cb) || !isfinite(ca)) return SREF_EINVAL;
+    double *rn = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *vn = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!rn || !vn) {
+        free(rn);
+        free(vn);
+        return SREF_EINVAL;
+    }
+    int status = SREF_OK;
+#pragma omp parallel for schedule(dynamic, 4) reduction(min : status)
+    for (int64_t i = 0; i < n; ++i) {
+        int e = stage_row(n, m, r, v, t, cb, ca, G, i, rn + 3 * i, vn + 3 * i);
+        if (e < status) status = e;
+    }
+    if (status == SREF_OK && (!all_finite(rn, 3 * n) || !all_finite(vn, 3 * n)))
+        status = SREF_ENONFINITE;
+    if (status == SREF_OK) {
+        memcpy(r, rn, sizeof(double) * 3 * (size_t)n);
+        memcpy(v, vn, sizeof(double) * 3 * (size_t)n);
+    }
+    free(rn);
+    free(vn);
+    return status;
+}
+
+/* Free drift of every particle by d (eqs. 27a, 27d). */
+static void drift(int64_t n, double *r, const double *v, double d)
+{
+    for (int64_t i = 0; i < 3 * n; ++i) r[i] = r[i] + d * v[i];
+}
+
+/* eq. (24): drift tau/2, W(tau/2) with eq. (19b) pairs, W(tau/2) with eq.
+ * (19a) pairs, drift tau/2.  On error r and v are left unchanged. */
+static int unmerged_step(int64_t n, const double *m, double *r, double *v, double tau,
+                         double G)
+{
+    double h = 0.5 * tau;
+    double *r1 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *v1 = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!r1 || !v1) {
+        free(r1);
+        free(v1);
+        return SREF_EINVAL;
+    }
+    memcpy(r1, r, sizeof(double) * 3 * (size_t)n);
+    memcpy(v1, v, sizeof(double) * 3 * (size_t)n);
+    drift(n, r1, v1, h);
+    int rc = sref_w_stage(n, m, r1, v1, h, h, 0.0, G);   /* eq. (19b) */
+    if (!rc) rc = sref_w_stage(n, m, r1, v1, h, 0.0, h, G); /* eq. (19a) */
+    if (!rc) {
+        drift(n, r1, v1, h);
+        if (!all_finite(r1, 3 * n)) rc = SREF_ENONFINITE;
+    }
+    if (!rc) {
+        memcpy(r, r1, sizeof(double) * 3 * (size_t)n);
+        memcpy(v, v1, sizeof(double) * 3 * (size_t)n);
+    }
+    free(r1);
+    free(v1);
+    return rc;
+}
+
+int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double tau,
+                       int64_t nsteps, double G, int scheme)
+{
+    if (nsteps < 0) return SREF_EINVAL;
+    if (scheme < SREF_SCHEME_PSI || scheme > SREF_SCHEME_TRIPLE_JUMP) return SREF_EINVAL;
+    int rc = check_args(n, m, r, v, tau, G);
+    if (rc) return rc;
+    /* Yoshida's triple jump: the outer weights g1 and the inner g0 sum to one
+     * and cancel the third-order error of a symmetric second-order step,
+     * 2 g1^3 + g0^3 = 0. */
+    const double g1 = 1.0 / (2.0 - cbrt(2.0));
+    const double g0 = 1.0 - 2.0 * g1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (scheme == SREF_SCHEME_PSI) {
+            rc = sref_step(n, m, r, v, tau, G, SREF_SOLVER_KEPLER);
+        } else if (scheme == SREF_SCHEME_UNMERGED) {
+            rc = unmerged_step(n, m, r, v, tau, G);
+        } else {
+            rc = sref_step(n, m, r, v, g1 * tau, G, SREF_SOLVER_KEPLER);
+            if (!rc) rc = sref_step(n, m, r, v, g0 * tau, G, SREF_SOLVER_KEPLER);
+            if (!rc) rc = sref_step(n, m, r, v, g1 * tau, G, SREF_SOLVER_KEPLER);
+        }
         if (rc) return rc;
     }
     return SREF_OK;

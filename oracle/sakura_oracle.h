@@ -65,6 +65,38 @@ int sref_step_rows(int64_t n, const double *m, const double *r, const double *v,
 int sref_evolve(int64_t n, const double *m, double *r, double *v, double tau,
                 int64_t nsteps, double G, int solver);
 
+/* Compositions of the step over tau (Sec. 2.2).
+ *  PSI          eq. (25) with the pair map of eq. (26): sref_step.
+ *  UNMERGED     eq. (24) as written: drift tau/2; a W stage over tau/2 whose
+ *               pair increments come from eq. (19b) (back-drift, then Kepler
+ *               flow); a W stage over tau/2 from eq. (19a) (Kepler flow, then
+ *               back-drift); drift tau/2.  Either reading of the operator order
+ *               gives this one sequence of maps in time.
+ *  TRIPLE_JUMP  the symmetric composition Psi(g1 tau) Psi(g0 tau) Psi(g1 tau)
+ *               suggested in Sec. 2.2 for higher order (Yoshida 1990),
+ *               g1 = 1 / (2 - 2^(1/3)), g0 = 1 - 2 g1.                        */
+#define SREF_SCHEME_PSI         0
+#define SREF_SCHEME_UNMERGED    1
+#define SREF_SCHEME_TRIPLE_JUMP 2
+
+/* Relative increments of one pair under the map: back-drift the relative
+ * position by cb, Kepler flow over t, back-drift by ca (eqs. 17, 18); minus
+ * the starting relative state.  eq. (26): (t, cb, ca) = (tau, tau/2, tau/2);
+ * eq. (19b): (tau, tau, 0); eq. (19a): (tau, 0, tau). */
+int sref_pair_map(double t, double cb, double ca, double G, double mi, double mj,
+                  const double ri[3], const double vi[3], const double rj[3],
+                  const double vj[3], double dr[3], double dv[3]);
+
+/* One W stage, eq. (23) with the pair map (t, cb, ca) of sref_pair_map and no
+ * drifts: r_i += sum_j mu_ij/m_i dr_ij, v_i += sum_j mu_ij/m_i dv_ij.  In
+ * place; unchanged on error. */
+int sref_w_stage(int64_t n, const double *m, double *r, double *v, double t, double cb,
+                 double ca, double G);
+
+/* nsteps steps of the given composition scheme. */
+int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double tau,
+                       int64_t nsteps, double G, int scheme);
+
 /* out[12] = {E, K, U, P[3], L[3], Rcm[3]} with long-double accumulation. */
 int sref_energy(int64_t n, const double *m, const double *r, const double *v,
                 double G, double out[12]);
