@@ -621,8 +621,10 @@ int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double 
     if (rc) return rc;
     /* Yoshida's triple jump: the outer weights g1 and the inner g0 sum to one
      * and cancel the third-order error of a symmetric second-order step,
-     * 2 g1^3 + g0^3 = 0. */
-    const double g1 = 1.0 / (2.0 - cbrt(2.0));
+     * 2 g1^3 + g0^3 = 0.  g1 = 1/(2 - 2^(1/3)) = 1.35120719195965763..., here
+     * its correctly rounded double (the libm expression can be 1-2 ulps off);
+     * g0 = 1 - 2 g1 is exact in double. */
+    const double g1 = 0x1.59e8b6eb96338p+0;
     const double g0 = 1.0 - 2.0 * g1;
     for (int64_t s = 0; s < nsteps; ++s) {
         if (scheme == SREF_SCHEME_PSI) {
