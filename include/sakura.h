@@ -101,6 +101,33 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                   double dt, int64_t nsteps, double G, void *stream,
                   sakura_stats *stats);
 
+/* Compositions of the step (Sec. 2.2).  A W stage applies eqs. (27b, 27c)
+ * with a pair map made of a back-drift cb of the relative position, the Kepler
+ * flow over t and a back-drift ca (t = cb + ca); stages are separated by free
+ * drifts of every particle.  One step over dt is:
+ *   SAKURA_SCHEME_PSI          eq. (25) with the pair map of eq. (26): drift
+ *                              dt/2, stage (dt; dt/2, dt/2), drift dt/2
+ *                              (= sakura_evolve).
+ *   SAKURA_SCHEME_UNMERGED     eq. (24): drift dt/2, stage (dt/2; dt/2, 0)
+ *                              (pairs by eq. 19b), stage (dt/2; 0, dt/2) (pairs
+ *                              by eq. 19a), drift dt/2.  Two pair launches.
+ *   SAKURA_SCHEME_TRIPLE_JUMP  Psi(g1 dt) Psi(g0 dt) Psi(g1 dt),
+ *                              g1 = 1/(2 - 2^(1/3)), g0 = 1 - 2 g1 < 0 (the
+ *                              higher-order composition the paper proposes,
+ *                              after Yoshida 1990).  Three pair launches.
+ * In exact arithmetic the unmerged step over dt equals two merged steps over
+ * dt/2 (a drift moves through a stage by shifting its back-drifts), and since
+ * the merged step is time-symmetric only up to a fourth-order defect for
+ * N > 2, the triple jump is third order, not fourth.
+ * stats count every pair launch (pair_launches = nsteps x stages) and
+ * failed_step names the step, not the stage.  Other arguments, errors and
+ * ownership as sakura_evolve; an unknown scheme is SAKURA_EINVAL. */
+enum { SAKURA_SCHEME_PSI = 0, SAKURA_SCHEME_UNMERGED = 1, SAKURA_SCHEME_TRIPLE_JUMP = 2 };
+
+int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, double *v,
+                         double dt, int64_t nsteps, double G, int scheme, void *stream,
+                         sakura_stats *stats);
+
 /* Batched ensembles: nsys independent systems, each of 1..64 particles, stored
  * back to back (CSR): system s owns particles offsets[s] .. offsets[s+1]-1 of
  * m, r, v.  offsets is a HOST array of nsys + 1 entries with offsets[0] = 0;

@@ -7,8 +7,9 @@
 //     block L of the weighted increment component c (dr xyz, dv xyz) received by
 //     particle 64 K + l from pairs with block L (the diagonal block for L = K).
 // Per step: k_pairs (eqs. 26, 23 over all unordered pairs) then k_apply
-// (eqs. 27b-d and the next step's 27a); k_import / k_export convert between the
-// caller's [n][3] arrays and the internal layout once per call.
+// (eqs. 27b-d and the next step's 27a); a composition of the step (Sec. 2.2)
+// runs one such pair of launches per stage.  k_import / k_export convert
+// between the caller's [n][3] arrays and the internal layout once per call.
 #include "common.hpp"
 
 #include <algorithm>
@@ -143,13 +144,19 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 // diagonal tile runs s = 1..32 (s = 32 on half the lanes), which visits each
 // pair i < j once.  Partial sums go to part[I][J] (i side) and part[J][I]
 // (j side).
+// The pair map is the back-drift cb of the relative position, the Kepler flow
+// over tau and the back-drift ca (eq. 26: cb = ca = tau/2; eq. 19b: cb = tau,
+// ca = 0; eq. 19a: cb = 0, ca = tau), with tau = cb + ca, which every
+// composition of the step satisfies exactly; the increments below are written
+// for that case.
 // MODE selects the starter: 0 plain; with a loaded network 1 plain with
 // domain statistics, 3 plain with harvest rows, 4 pairs that may lie in the
 // network's domain listed for k_deferred (which starts those in the domain
 // from the network) and the rest solved plainly.
 template <bool HIST, int MODE, bool DEFKP = false>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
-                                                double G, const double *__restrict__ S,
+                                                double cb, double ca, double G,
+                                                const double *__restrict__ S,
                                                 double *__restrict__ part,
                                                 DevCounters *cnt, SlotStats *slots,
                                                 kep::KeplerParams kp, long long step,
@@ -187,7 +194,6 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     if (HIST && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
-    const double h = 0.5 * tau;
     const double wgt_j = G * xi[6];
     const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
     const int nj = n - J * TILE; // valid j slots in this block
@@ -215,18 +221,18 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const double msum = mi + mj;
         const bool act = valid_i && (q < nj) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
-        // relative state and the pair back-drift of eq. (17) by tau/2
+        // relative state and the pair back-drift of eq. (17) by cb
         double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q],
                w2 = xi[5] - sj[5][q];
-        double x0 = fma(-h, w0, xi[0] - sj[0][q]);
-        double x1 = fma(-h, w1, xi[1] - sj[1][q]);
-        double x2 = fma(-h, w2, xi[2] - sj[2][q]);
+        double x0 = fma(-cb, w0, xi[0] - sj[0][q]);
+        double x1 = fma(-cb, w1, xi[1] - sj[1][q]);
+        double x2 = fma(-cb, w2, xi[2] - sj[2][q]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
         bool live = act && !collide;
         // lanes without a pair solve a trivial problem (tau = 0, |x0| = 1; any
         // finite mu): the starter is s = 0, where t(s) = 0 holds at once
-        double d[6]; // increment of eq. (26) less the starting relative state, per unit mu
+        double d[6]; // increment of the pair map less the starting relative state, per unit mu
         unsigned info;
         if constexpr (MODE == 4) {
             // Pairs that may lie in the network's domain (a necessary condition
@@ -252,8 +258,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                                                  w2, live ? r0sq : 1.0)
                       : kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2,
                                          live ? r0sq : 1.0, kp);
-            const double a = fma(-h, f.fdot, f.fm1);
-            const double b = fma(-h, f.gdm1, f.gmt);
+            const double a = fma(-ca, f.fdot, f.fm1);
+            const double b = fma(-ca, f.gdm1, f.gmt);
             d[0] = fma(a, x0, b * w0);
             d[1] = fma(a, x1, b * w1);
             d[2] = fma(a, x2, b * w2);
@@ -283,12 +289,12 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 w0 = xi[3] - sj[3][q];
                 w1 = xi[4] - sj[4][q];
                 w2 = xi[5] - sj[5][q];
-                x0 = fma(-h, w0, xi[0] - sj[0][q]);
-                x1 = fma(-h, w1, xi[1] - sj[1][q]);
-                x2 = fma(-h, w2, xi[2] - sj[2][q]);
+                x0 = fma(-cb, w0, xi[0] - sj[0][q]);
+                x1 = fma(-cb, w1, xi[1] - sj[1][q]);
+                x2 = fma(-cb, w2, xi[2] - sj[2][q]);
             }
-            const double a = fma(-h, f.fdot, f.fm1);
-            const double b = fma(-h, f.gdm1, f.gmt);
+            const double a = fma(-ca, f.fdot, f.fm1);
+            const double b = fma(-ca, f.gdm1, f.gmt);
             d[0] = fma(a, x0, b * w0);
             d[1] = fma(a, x1, b * w1);
             d[2] = fma(a, x2, b * w2);
@@ -352,7 +358,8 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
 // are added to the tile's partial sums in list order, one lane per component,
 // so the result does not depend on the order in which tiles are taken.
 // Persistent: every wave leaves once the list is exhausted.
-__global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, double G,
+__global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, double cb,
+                                                   double ca, double G,
                                                    const double *__restrict__ S,
                                                    double *__restrict__ part, DevCounters *cnt,
                                                    SlotStats *slots, kep::KeplerParams kp,
@@ -365,7 +372,6 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
     const double *M = S;
     const double *V = S + 4 * (size_t)np;
     const double *XH = S + 7 * (size_t)np;
-    const double h = 0.5 * tau;
     unsigned long long n_solve = 0, n_fb = 0;
     unsigned it_sum = 0, it_max = 0;
     GuessCount gc;
@@ -392,17 +398,17 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
         const double msum = mi + mj;
         const double w0 = V[i] - V[j], w1 = V[np + i] - V[np + j],
                      w2 = V[2 * (size_t)np + i] - V[2 * (size_t)np + j];
-        const double x0 = fma(-h, w0, XH[i] - XH[j]);
-        const double x1 = fma(-h, w1, XH[np + i] - XH[np + j]);
-        const double x2 = fma(-h, w2, XH[2 * (size_t)np + i] - XH[2 * (size_t)np + j]);
+        const double x0 = fma(-cb, w0, XH[i] - XH[j]);
+        const double x1 = fma(-cb, w1, XH[np + i] - XH[np + j]);
+        const double x2 = fma(-cb, w2, XH[2 * (size_t)np + i] - XH[2 * (size_t)np + j]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const double mu = has ? G * msum : 0.0;
         const double s_net = kep::net_starter(net, tau, mu, x0, x1, x2, w0, w1, w2, r0sq);
         kep::NetGuess<2> gp(net, i, j, s_net);
         const kep::PairFlow f = kep::kepler_flow(has ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2,
                                                  has ? r0sq : 1.0, kp, gp);
-        const double a = fma(-h, f.fdot, f.fm1);
-        const double b = fma(-h, f.gdm1, f.gmt);
+        const double a = fma(-ca, f.fdot, f.fm1);
+        const double b = fma(-ca, f.gdm1, f.gmt);
         const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
                              fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
                              fma(f.fdot, x2, f.gdm1 * w2)};
@@ -447,9 +453,12 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
 }
 
 // Deterministic compensated reduction of the partial sums of one block K
-// (fixed order L = 0..nb-1, TwoSum), then eqs. (27b-d) and the half drift
-// (27a) of the next step.  Wave c of the workgroup reduces component c.
-__global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, double h,
+// (fixed order L = 0..nb-1, TwoSum), then eqs. (27b-d): the drift h_after
+// that ends the stage, and the drift h_next that begins the next one (27a of
+// the next step; both tau/2 for eq. 25).  Wave c of the workgroup reduces
+// component c.
+__global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, double h_after,
+                                                    double h_next,
                                                     double *__restrict__ S,
                                                     const double *__restrict__ part,
                                                     DevCounters *cnt, long long step)
@@ -496,10 +505,10 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, doubl
         const size_t o = (size_t)k * np + i;
         const double rt = XH[o] + dsum[k][lane];    // (27b)
         const double v1 = V[o] + dsum[3 + k][lane]; // (27c)
-        const double x1 = rt + h * v1;              // (27d)
+        const double x1 = rt + h_after * v1;        // (27d)
         X[o] = x1;
         V[o] = v1;
-        XH[o] = x1 + h * v1; // (27a) of the next step
+        XH[o] = x1 + h_next * v1; // (27a) of the next stage
         fin = fin && isfinite(x1) && isfinite(v1);
     }
     if (!fin) record_error(cnt, ST_NONFINITE, step);
@@ -624,44 +633,87 @@ __global__ void k_energy_final(int ntiles, int nblk, double G, const double *__r
 
 template <bool HIST>
 void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
-                    double G, const double *S, double *part, DevCounters *cnt, SlotStats *slots,
-                    kep::KeplerParams kp, long long step, const kep::GuessNet &net)
+                    double cb, double ca, double G, const double *S, double *part,
+                    DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
+                    const kep::GuessNet &net)
 {
     // the plain solve with the default parameters built in, where they apply
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
+#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp, step, net
     switch (mode) {
     case 1:
-        k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         break;
     case 2: // the network's starter: pairs of its domain go through k_deferred
-        if (defkp)
-            k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
-                                                            step, net);
-        else
-            k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
-                                                      step, net);
-        k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, G, S, part, cnt, slots, kp,
-                                                          step, net);
+        if (defkp) k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        else k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, cb, ca, G, S, part, cnt,
+                                                          slots, kp, step, net);
         break;
     case 3:
-        k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+        k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         break;
     default:
-        if (defkp)
-            k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
-                                                            step, net);
-        else
-            k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(n, nb, np, dt, G, S, part, cnt, slots, kp,
-                                                      step, net);
+        if (defkp) k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        else k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
     }
+#undef SAKURA_PAIR_ARGS
 }
 
 void launch_pairs(bool hist, int mode, int ntiles, hipStream_t st, int n, int nb, int np,
-                  double dt, double G, const double *S, double *part, DevCounters *cnt,
-                  SlotStats *slots, kep::KeplerParams kp, long long step, const kep::GuessNet &net)
+                  double dt, double cb, double ca, double G, const double *S, double *part,
+                  DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
+                  const kep::GuessNet &net)
 {
-    if (hist) launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
-    else launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, G, S, part, cnt, slots, kp, step, net);
+    if (hist)
+        launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp,
+                             step, net);
+    else
+        launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp,
+                              step, net);
+}
+
+// One W stage of a composition of the step (Sec. 2.2): the pair map (flow
+// time t, back-drifts cb before and ca after, t = cb + ca), the drift that
+// ends the stage and the drift that begins the next one.
+struct Stage {
+    double t, cb, ca, after, next;
+};
+
+// The stages of one step over dt and the drift that begins the first.
+//  eq. (25) with the pair map of eq. (26): one stage.
+//  eq. (24): a stage over dt/2 with eq. (19b) pairs (back-drift first) and one
+//    with eq. (19a) pairs (back-drift last), no drift between them.
+//  triple jump of eq. (25): steps over g1 dt, g0 dt, g1 dt (Yoshida 1990).
+int scheme_stages(int scheme, double dt, Stage st[3], int &count, double &first)
+{
+    const double h = 0.5 * dt;
+    switch (scheme) {
+    case SAKURA_SCHEME_PSI:
+        st[0] = {dt, h, h, h, h};
+        count = 1;
+        first = h;
+        return SAKURA_OK;
+    case SAKURA_SCHEME_UNMERGED:
+        st[0] = {h, h, 0.0, 0.0, 0.0};
+        st[1] = {h, 0.0, h, h, h};
+        count = 2;
+        first = h;
+        return SAKURA_OK;
+    case SAKURA_SCHEME_TRIPLE_JUMP: {
+        // g1 = 1/(2 - 2^(1/3)) correctly rounded; g0 = 1 - 2 g1 (exact in double)
+        const double g1 = 0x1.59e8b6eb96338p+0, g0 = 1.0 - 2.0 * g1;
+        const double t1 = g1 * dt, t0 = g0 * dt, h1 = 0.5 * t1, h0 = 0.5 * t0;
+        st[0] = {t1, h1, h1, h1, h0};
+        st[1] = {t0, h0, h0, h0, h1};
+        st[2] = {t1, h1, h1, h1, h1};
+        count = 3;
+        first = h1;
+        return SAKURA_OK;
+    }
+    default:
+        return SAKURA_EINVAL;
+    }
 }
 
 int need_events(sakura_t *h, size_t count)
@@ -737,8 +789,9 @@ void sakura_destroy(sakura_t *h)
 
 const char *sakura_last_error(const sakura_t *h) { return h ? h->err.c_str() : "null handle"; }
 
-int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
-                  int64_t nsteps, double G, void *stream, sakura_stats *stats)
+int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, double *v,
+                         double dt, int64_t nsteps, double G, int scheme, void *stream,
+                         sakura_stats *stats)
 {
     if (!h) return SAKURA_EINVAL;
     h->err.clear();
@@ -751,6 +804,11 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     if (!std::isfinite(dt) || !std::isfinite(G) || G < 0.0)
         return sk::fail(h, SAKURA_EINVAL, "dt and G must be finite and G >= 0");
     if (nsteps < 0) return sk::fail(h, SAKURA_EINVAL, "nsteps < 0");
+    Stage stages[3];
+    int nstage = 0;
+    double first = 0.0;
+    if (scheme_stages(scheme, dt, stages, nstage, first))
+        return sk::fail(h, SAKURA_EINVAL, "unknown composition scheme");
     if (nsteps == 0) return SAKURA_OK;
 
     SAKURA_HIP(h, hipSetDevice(h->device));
@@ -761,9 +819,9 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
     if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE))) return rc;
     const bool timing = stats != nullptr;
-    if (timing && (rc = need_events(h, 2 + 2 * (size_t)nsteps))) return rc;
+    const int64_t nlaunch = nsteps * nstage;
+    if (timing && (rc = need_events(h, 2 + 2 * (size_t)nlaunch))) return rc;
 
-    const double half = 0.5 * dt;
     const int ntiles = nb * (nb + 1) / 2;
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
@@ -780,13 +838,18 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
     sk::k_clear<<<1, sk::NSLOT, 0, st>>>(h->cnt, h->slots);
-    k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, half, h->state, h->cnt);
+    k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, first, h->state, h->cnt);
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * s], st));
-        launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, dt, G, h->state,
-                     h->part, h->cnt, h->slots, kp, s, net);
-        if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * s], st));
-        k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, half, h->state, h->part, h->cnt, s);
+        for (int k = 0; k < nstage; ++k) {
+            const Stage &g = stages[k];
+            const int64_t e = s * nstage + k;
+            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * e], st));
+            launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, g.t, g.cb,
+                         g.ca, G, h->state, h->part, h->cnt, h->slots, kp, s, net);
+            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * e], st));
+            k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, h->state,
+                                                 h->part, h->cnt, s);
+        }
     }
     k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, h->state, r, v, h->cnt);
     sk::k_fold_stats<<<1, sk::NSLOT, 0, st>>>(h->slots, h->cnt);
@@ -803,12 +866,12 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
         stats->iters_max = c.iters_max;
         sk::guess_stats(c, stats);
         for (int k = 0; k < 32; ++k) stats->hist[k] = c.hist[k];
-        stats->pair_launches = nsteps;
+        stats->pair_launches = nlaunch;
         stats->failed_step = c.status ? c.failed_step : -1;
         float ms = 0.0f;
         double tot = 0.0;
-        for (int64_t s = 0; s < nsteps; ++s) {
-            SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[2 + 2 * s], h->events[3 + 2 * s]));
+        for (int64_t e = 0; e < nlaunch; ++e) {
+            SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[2 + 2 * e], h->events[3 + 2 * e]));
             tot += ms;
         }
         stats->pair_kernel_ms = tot;
@@ -819,6 +882,12 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
     if (code) return sk::fail(h, code, std::string(sk::status_text(code)) + " at step " +
                                        std::to_string(c.failed_step));
     return SAKURA_OK;
+}
+
+int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
+                  int64_t nsteps, double G, void *stream, sakura_stats *stats)
+{
+    return sakura_evolve_scheme(h, n, m, r, v, dt, nsteps, G, SAKURA_SCHEME_PSI, stream, stats);
 }
 
 int sakura_step(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,

@@ -19,6 +19,7 @@ OK, EINVAL, ENONFINITE, ECOLLIDE, ENOCONV, EHIP, ENOMEM, ENOMODEL = 0, -1, -2, -
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ECOLLIDE", -4: "ENOCONV",
                -5: "EHIP", -6: "ENOMEM", -7: "ENOMODEL"}
 GUESS_ANALYTIC, GUESS_LEARNED = 0, 1
+SCHEME_PSI, SCHEME_UNMERGED, SCHEME_TRIPLE_JUMP = 0, 1, 2
 
 
 class SakuraError(RuntimeError):
@@ -108,6 +109,10 @@ def load_library():
     L.sakura_evolve.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int64,
                                 ctypes.c_double, P, ctypes.POINTER(Stats)]
     L.sakura_evolve.restype = ctypes.c_int
+    L.sakura_evolve_scheme.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
+                                       ctypes.c_int64, ctypes.c_double, ctypes.c_int, P,
+                                       ctypes.POINTER(Stats)]
+    L.sakura_evolve_scheme.restype = ctypes.c_int
     L.sakura_energy.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), P]
     L.sakura_energy.restype = ctypes.c_int
@@ -206,6 +211,21 @@ class Sakura:
                                      ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
                                      float(dt), int(nsteps), float(G), self._stream(m),
                                      ctypes.byref(st) if stats else None)
+        if rc != OK:
+            self._raise(rc)
+        return st.to_dict() if stats else None
+
+    def evolve_scheme(self, m, r, v, dt: float, nsteps: int, scheme: int, G: float = 1.0,
+                      stats: bool = False):
+        """nsteps steps of a composition of the step (SCHEME_PSI, SCHEME_UNMERGED,
+        SCHEME_TRIPLE_JUMP); r, v updated in place."""
+        n = _check_state(m, r, v)
+        st = Stats()
+        rc = self._lib.sakura_evolve_scheme(self._h, n, ctypes.c_void_p(m.data_ptr()),
+                                            ctypes.c_void_p(r.data_ptr()),
+                                            ctypes.c_void_p(v.data_ptr()), float(dt),
+                                            int(nsteps), float(G), int(scheme), self._stream(m),
+                                            ctypes.byref(st) if stats else None)
         if rc != OK:
             self._raise(rc)
         return st.to_dict() if stats else None
