@@ -273,6 +273,58 @@ def accuracy_study(torch):
             "seconds": time.perf_counter() - t0}
 
 
+SCHEME_NAMES = {0: "psi", 1: "unmerged", 2: "triple_jump"}
+SCHEME_STAGES = {0: 1, 1: 2, 2: 3}
+
+
+def schemes(lib, torch, m, r, v, tau, steps=32, warmup=8):
+    """The compositions of the step (Sec. 2.2) on the GPU: throughput of each
+    on the benchmark workload (every stage is one launch of the tile kernel),
+    and the convergence order each reaches on a 64-star Plummer sphere over
+    1/8 time unit (self-convergence against the triple jump with 16x smaller
+    steps)."""
+    from paper_1402_3325_amd import workloads
+    n = len(m)
+    pairs = n * (n - 1) // 2
+    out = {}
+    mt = torch.tensor(m, dtype=torch.float64, device="cuda")
+    for sid, name in SCHEME_NAMES.items():
+        rt = torch.tensor(r, dtype=torch.float64, device="cuda")
+        vt = torch.tensor(v, dtype=torch.float64, device="cuda")
+        lib.evolve_scheme(mt, rt, vt, tau, warmup, sid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = lib.evolve_scheme(mt, rt, vt, tau, steps, sid, stats=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"pair_solves_per_s": st["pair_solves"] / wall,
+                     "ms_per_step": wall * 1e3 / steps,
+                     "pair_launches_per_step": st["pair_launches"] / steps,
+                     "pair_kernel_ms": st["pair_kernel_ms"] / max(st["pair_launches"], 1),
+                     "mean_kepler_iters": st["iters_total"] / max(st["pair_solves"], 1)}
+    ms, rs, vs, _ = workloads.plummer(64, rng=np.random.default_rng(64))
+    T = 0.125
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    def run(sid, nsteps):
+        rt, vt = dev(rs), dev(vs)
+        lib.evolve_scheme(dev(ms), rt, vt, T / nsteps, nsteps, sid)
+        return rt.cpu().numpy()
+
+    ref = run(2, 1024)
+    rrms = float(np.sqrt(np.mean(np.sum(rs ** 2, axis=1))))
+    conv = {}
+    for sid, name in SCHEME_NAMES.items():
+        errs = [float(np.max(np.abs(run(sid, k) - ref))) / rrms for k in (16, 32, 64)]
+        conv[name] = {"steps": [16, 32, 64],
+                      "pair_solves": [k * SCHEME_STAGES[sid] * 64 * 63 // 2 for k in (16, 32, 64)],
+                      "err_r": errs,
+                      "order": [float(np.log2(errs[i] / errs[i + 1])) for i in range(2)]}
+    out["convergence"] = {"workload": "64-star Plummer sphere, T = 1/8, reference: triple jump "
+                                      "with 1024 steps", "by_scheme": conv}
+    return out
+
+
 def cpu_baseline(m, r, v, tau, budget_s=15.0):
     """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
     a bounded sample: rows of one step of the same workload."""
@@ -306,6 +358,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-schemes", action="store_true")
     ap.add_argument("--harvest-steps", type=int, default=2000)
     ap.add_argument("--accuracy", action="store_true",
                     help="only run the accuracy studies (energy error vs mass ratio and "
@@ -400,6 +453,8 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
         "err_vs_oracle": parity,
     }
+    if not args.no_schemes:
+        out["schemes"] = schemes(lib, torch, m, r, v, tau)
     if not args.no_batched:
         out["batched"] = batched(lib, torch)
     if not args.no_learned:
