@@ -60,6 +60,12 @@ def lib():
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.sref_evolve_scheme.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
                                          ctypes.c_int64, ctypes.c_double, ctypes.c_int]
+        L.sref_pair_is_close.argtypes = [ctypes.c_double] * 4 + [_D, _D, ctypes.c_double]
+        L.sref_step_hybrid.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _I64]
+        L.sref_step_rows_hybrid.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                            _I64, _D, _D]
         L.sref_energy.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]
         L.sref_num_threads.restype = ctypes.c_int
         L.sref_mlp_forward.argtypes = [_D, ctypes.c_int64, _D, _D]
@@ -179,6 +185,43 @@ def evolve_scheme(m, r, v, tau, nsteps, scheme, G=1.0):
     if rc:
         raise OracleError(rc, "sref_evolve_scheme")
     return r, v
+
+
+def pair_is_close(tau, G, mi, mj, X, W, eta):
+    """The close-pair test of the hybrid step (Kepler map when True)."""
+    X = _f64(X, (3,)).copy()
+    W = _f64(W, (3,)).copy()
+    return bool(lib().sref_pair_is_close(float(tau), float(G), float(mi), float(mj), _p(X),
+                                         _p(W), float(eta)))
+
+
+def step_hybrid(m, r, v, tau, eta, G=1.0):
+    """One hybrid step; returns (r, v, number of Kepler pairs)."""
+    m = _f64(m)
+    n = m.shape[0]
+    r = _f64(r, (n, 3)).copy()
+    v = _f64(v, (n, 3)).copy()
+    nk = ctypes.c_int64(0)
+    rc = lib().sref_step_hybrid(n, _p(m), _p(r), _p(v), float(tau), float(G), float(eta),
+                                ctypes.byref(nk))
+    if rc:
+        raise OracleError(rc, "sref_step_hybrid")
+    return r, v, nk.value
+
+
+def step_rows_hybrid(m, r, v, tau, eta, rows, G=1.0):
+    m = _f64(m)
+    n = m.shape[0]
+    r = _f64(r, (n, 3))
+    v = _f64(v, (n, 3))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    ro = np.empty((rows.shape[0], 3))
+    vo = np.empty((rows.shape[0], 3))
+    rc = lib().sref_step_rows_hybrid(n, _p(m), _p(r), _p(v), float(tau), float(G), float(eta),
+                                     rows.shape[0], rows.ctypes.data_as(_I64), _p(ro), _p(vo))
+    if rc:
+        raise OracleError(rc, "sref_step_rows_hybrid")
+    return ro, vo
 
 
 def step_rows(m, r, v, tau, rows, G=1.0):

@@ -642,6 +642,132 @@ int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Close-pair hybrid: the Kepler map of eq. (26) for close pairs, the eq. (28) */
+/* drift-kick-drift map for the rest.                                        */
+/* ------------------------------------------------------------------------ */
+int sref_pair_is_close(double tau, double G, double mi, double mj, const double X[3],
+                       const double W[3], double eta)
+{
+    double mu = G * (mi + mj);
+    double r2 = X[0] * X[0] + X[1] * X[1];
+    r2 = r2 + X[2] * X[2];
+    double w2 = W[0] * W[0] + W[1] * W[1];
+    w2 = w2 + W[2] * W[2];
+    double t2 = tau * tau;
+    double e2 = eta * eta;
+    double e4 = e2 * e2;
+    double A = t2 * mu;
+    double r3 = (r2 * r2) * r2;
+    /* tau sqrt(mu / r^3) > eta, squared twice */
+    if (A * A > e4 * r3) return 1;
+    /* tau |W| / r > eta, squared */
+    if (t2 * w2 > e2 * r2) return 1;
+    return 0;
+}
+
+/* Row i of the hybrid step from the half-drifted positions rh; *nk counts the
+ * Kepler pairs (i, j) with j > i. */
+static int hybrid_row(int64_t n, const double *m, const double *rh, const double *v,
+                      double tau, double G, double eta, int64_t i, double rn[3],
+                      double vn[3], int64_t *nk)
+{
+    long double ar[3] = {0.0L, 0.0L, 0.0L}, av[3] = {0.0L, 0.0L, 0.0L};
+    int64_t kep = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double mij = m[i] + m[j];
+        if (mij == 0.0) continue;
+        double w = m[j] / mij;
+        double X[3], W[3];
+        for (int c = 0; c < 3; ++c) {
+            X[c] = rh[3 * i + c] - rh[3 * j + c];
+            W[c] = v[3 * i + c] - v[3 * j + c];
+        }
+        int close = sref_pair_is_close(tau, G, m[i], m[j], X, W, eta);
+        if (close && j > i) ++kep;
+        double dr[3], dv[3];
+        int rc = sref_pair_increment(tau, G, m[i], m[j], rh + 3 * i, v + 3 * i, rh + 3 * j,
+                                     v + 3 * j, close ? SREF_SOLVER_KEPLER : SREF_SOLVER_DKD,
+                                     dr, dv);
+        if (rc) return rc;
+        for (int c = 0; c < 3; ++c) {
+            ar[c] += (long double)w * (long double)dr[c];
+            av[c] += (long double)w * (long double)dv[c];
+        }
+    }
+    double h = 0.5 * tau;
+    for (int c = 0; c < 3; ++c) {
+        double rt = (double)((long double)rh[3 * i + c] + ar[c]); /* 27b */
+        vn[c] = (double)((long double)v[3 * i + c] + av[c]);      /* 27c */
+        rn[c] = rt + h * vn[c];                                   /* 27d */
+    }
+    if (nk) *nk = kep;
+    return SREF_OK;
+}
+
+int sref_step_hybrid(int64_t n, const double *m, double *r, double *v, double tau,
+                     double G, double eta, int64_t *n_kepler)
+{
+    int rc = check_args(n, m, r, v, tau, G);
+    if (rc) return rc;
+    if (!(eta > 0.0) || !isfinite(eta)) return SREF_EINVAL;
+    double *rh = half_drift(n, r, v, tau);
+    double *rn = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *vn = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!rh || !rn || !vn) {
+        free(rh);
+        free(rn);
+        free(vn);
+        return SREF_EINVAL;
+    }
+    int status = SREF_OK;
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(min : status) reduction(+ : total)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t nk = 0;
+        int e = hybrid_row(n, m, rh, v, tau, G, eta, i, rn + 3 * i, vn + 3 * i, &nk);
+        if (e < status) status = e;
+        total += nk;
+    }
+    if (status == SREF_OK && (!all_finite(rn, 3 * n) || !all_finite(vn, 3 * n)))
+        status = SREF_ENONFINITE;
+    if (status == SREF_OK) {
+        memcpy(r, rn, sizeof(double) * 3 * (size_t)n);
+        memcpy(v, vn, sizeof(double) * 3 * (size_t)n);
+        if (n_kepler) *n_kepler = total;
+    }
+    free(rh);
+    free(rn);
+    free(vn);
+    return status;
+}
+
+int sref_step_rows_hybrid(int64_t n, const double *m, const double *r, const double *v,
+                          double tau, double G, double eta, int64_t nrows,
+                          const int64_t *rows, double *r_out, double *v_out)
+{
+    int rc = check_args(n, m, r, v, tau, G);
+    if (rc) return rc;
+    if (!(eta > 0.0) || !isfinite(eta)) return SREF_EINVAL;
+    for (int64_t k = 0; k < nrows; ++k)
+        if (rows[k] < 0 || rows[k] >= n) return SREF_EINVAL;
+    double *rh = half_drift(n, r, v, tau);
+    if (!rh) return SREF_EINVAL;
+    int status = SREF_OK;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int e = hybrid_row(n, m, rh, v, tau, G, eta, rows[k], r_out + 3 * k, v_out + 3 * k,
+                           NULL);
+        if (e < status) status = e;
+    }
+    free(rh);
+    if (status) return status;
+    if (!all_finite(r_out, 3 * nrows) || !all_finite(v_out, 3 * nrows))
+        return SREF_ENONFINITE;
+    return SREF_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics: H = H_T + H_U of eqs. (1-3), momentum, angular momentum and  */
 /* centre of mass.  Row partial sums are combined serially for a result that */
 /* does not depend on the thread count.                                      */

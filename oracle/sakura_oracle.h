@@ -97,6 +97,32 @@ int sref_w_stage(int64_t n, const double *m, double *r, double *v, double t, dou
 int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double tau,
                        int64_t nsteps, double G, int scheme);
 
+/* Close-pair hybrid.  Sec. 1 names applying the Kepler solver only to a few
+ * close pairs as a possible optimisation, without a criterion.  A pair is
+ * close when the step is not small against its own time scales: with X, W the
+ * relative position and velocity after the half drift of eq. (27a), r2 = X.X,
+ * w2 = W.W, mu = G (mi + mj),
+ *     tau sqrt(mu / r^3) > eta   or   tau |W| / r > eta,
+ * evaluated without square roots as
+ *     (tau^2 mu)^2 > eta^4 r2^3   or   tau^2 w2 > eta^2 r2,
+ * every product rounded in the order written (t2 = tau*tau, e2 = eta*eta,
+ * e4 = e2*e2, r2 and w2 summed x, y, z left to right), no fused multiply-add.
+ * Close pairs take the Kepler map of eq. (26); the others the drift-kick-drift
+ * map of eq. (28), whose increments are dr = 0 and dv = tau a_ij in exact
+ * arithmetic.  eta > 0. */
+int sref_pair_is_close(double tau, double G, double mi, double mj, const double X[3],
+                       const double W[3], double eta);
+
+/* One step, eqs. (27a-d), with the hybrid pair maps.  *n_kepler (may be NULL)
+ * receives the number of unordered pairs solved by the Kepler map. */
+int sref_step_hybrid(int64_t n, const double *m, double *r, double *v, double tau,
+                     double G, double eta, int64_t *n_kepler);
+
+/* The hybrid step's state for the listed particles only (r, v unchanged). */
+int sref_step_rows_hybrid(int64_t n, const double *m, const double *r, const double *v,
+                          double tau, double G, double eta, int64_t nrows,
+                          const int64_t *rows, double *r_out, double *v_out);
+
 /* out[12] = {E, K, U, P[3], L[3], Rcm[3]} with long-double accumulation. */
 int sref_energy(int64_t n, const double *m, const double *r, const double *v,
                 double G, double out[12]);
