@@ -649,10 +649,8 @@ int sref_pair_is_close(double tau, double G, double mi, double mj, const double 
                        const double W[3], double eta)
 {
     double mu = G * (mi + mj);
-    double r2 = X[0] * X[0] + X[1] * X[1];
-    r2 = r2 + X[2] * X[2];
-    double w2 = W[0] * W[0] + W[1] * W[1];
-    w2 = w2 + W[2] * W[2];
+    double r2 = fma(X[0], X[0], fma(X[1], X[1], X[2] * X[2]));
+    double w2 = fma(W[0], W[0], fma(W[1], W[1], W[2] * W[2]));
     double t2 = tau * tau;
     double e2 = eta * eta;
     double e4 = e2 * e2;

@@ -106,7 +106,7 @@ int sref_evolve_scheme(int64_t n, const double *m, double *r, double *v, double 
  * evaluated without square roots as
  *     (tau^2 mu)^2 > eta^4 r2^3   or   tau^2 w2 > eta^2 r2,
  * every product rounded in the order written (t2 = tau*tau, e2 = eta*eta,
- * e4 = e2*e2, r2 and w2 summed x, y, z left to right), no fused multiply-add.
+ * e4 = e2*e2), r2 and w2 formed as fma(x, x, fma(y, y, z*z)).
  * Close pairs take the Kepler map of eq. (26); the others the drift-kick-drift
  * map of eq. (28), whose increments are dr = 0 and dv = tau a_ij in exact
  * arithmetic.  eta > 0. */
