@@ -325,6 +325,50 @@ def schemes(lib, torch, m, r, v, tau, steps=32, warmup=8):
     return out
 
 
+def hybrid(lib, torch, m, r, v, tau, steps, warmup, etas=(0.01, 0.03)):
+    """The close-pair hybrid on the benchmark workload: Kepler solves only for
+    pairs with tau sqrt(mu/r^3) > eta or tau |W|/r > eta, the eq. (28) kick
+    for the rest.  Pair interactions per second (every pair is still
+    interacted with each step), the Kepler pairs per step, and the accuracy
+    against the all-Kepler step over the same steps: relative energy change of
+    each run and their final-state difference."""
+    n = len(m)
+    pairs = n * (n - 1) // 2
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    mt = dev(m)
+    e0 = lib.energy(mt, dev(r), dev(v))["E"]
+    rk, vk = dev(r), dev(v)
+    lib.evolve(mt, rk, vk, tau, warmup + steps)
+    ek = lib.energy(mt, rk, vk)["E"]
+    rrms = float(np.sqrt(np.mean(np.sum(r ** 2, axis=1))))
+    out = {"workload": "the benchmark workload, warm-up + timed steps from the same start",
+           "kepler_all": {"dE_over_E": abs((ek - e0) / e0)}, "by_eta": {}}
+    for eta in etas:
+        rt, vt = dev(r), dev(v)
+        lib.set_hybrid(eta)
+        try:
+            lib.evolve(mt, rt, vt, tau, warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lib.evolve(mt, rt, vt, tau, steps, stats=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            lib.set_hybrid(0.0)
+        eh = lib.energy(mt, rt, vt)["E"]
+        dr = float((rt - rk).abs().max()) / rrms
+        out["by_eta"][str(eta)] = {
+            "pair_interactions_per_s": pairs * steps / wall,
+            "ms_per_step": wall * 1e3 / steps,
+            "pair_kernel_ms": st["pair_kernel_ms"] / max(st["pair_launches"], 1),
+            "kepler_pairs_per_step": st["pair_solves"] / steps,
+            "kicked_pairs_per_step": st["pair_kicks"] / steps,
+            "mean_kepler_iters": st["iters_total"] / max(st["pair_solves"], 1),
+            "dE_over_E": abs((eh - e0) / e0),
+            "max_dr_vs_kepler_all_over_rrms": dr}
+    return out
+
+
 def cpu_baseline(m, r, v, tau, budget_s=15.0):
     """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
     a bounded sample: rows of one step of the same workload."""
@@ -359,6 +403,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-schemes", action="store_true")
+    ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--harvest-steps", type=int, default=2000)
     ap.add_argument("--accuracy", action="store_true",
                     help="only run the accuracy studies (energy error vs mass ratio and "
@@ -455,6 +500,8 @@ def main():
     }
     if not args.no_schemes:
         out["schemes"] = schemes(lib, torch, m, r, v, tau)
+    if not args.no_hybrid:
+        out["hybrid"] = hybrid(lib, torch, m, r, v, tau, args.steps, args.warmup)
     if not args.no_batched:
         out["batched"] = batched(lib, torch)
     if not args.no_learned:

@@ -80,6 +80,8 @@ typedef struct {
     uint64_t guess_domain_iters; /* Kepler evaluations of those solves */
     uint64_t guess_learned;      /* solves started from the network's value */
     uint64_t guess_restarts;     /* of those, searches restarted from the plain starter */
+    /* Close-pair hybrid (zero unless sakura_set_hybrid is on): */
+    uint64_t pair_kicks; /* pairs given the eq. (28) kick instead of a Kepler solve */
 } sakura_stats;
 
 /* Create a handle on HIP device `device`; opts may be NULL (defaults).
@@ -127,6 +129,25 @@ enum { SAKURA_SCHEME_PSI = 0, SAKURA_SCHEME_UNMERGED = 1, SAKURA_SCHEME_TRIPLE_J
 int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                          double dt, int64_t nsteps, double G, int scheme, void *stream,
                          sakura_stats *stats);
+
+/* Close-pair hybrid.  Sec. 1 names applying the Kepler solver only to a few
+ * close pairs as a possible optimisation; the criterion is this library's.
+ * With eta > 0, the merged step (sakura_step, sakura_evolve,
+ * sakura_evolve_scheme with SAKURA_SCHEME_PSI) solves a pair by the Kepler map
+ * of eq. (26) only when the step is not small against the pair's own time
+ * scales,
+ *     tau sqrt(mu / r^3) > eta   or   tau |W| / r > eta,
+ * with X, W the relative position and velocity after the half drift of
+ * eq. (27a), r = |X|, mu = G (m_i + m_j); evaluated without square roots as
+ * (tau^2 mu)^2 > eta^4 r^6 or tau^2 |W|^2 > eta^2 r^2, every product rounded
+ * in that order and |X|^2, |W|^2 formed as fma(x, x, fma(y, y, z*z)).  Every
+ * other pair takes the drift-kick-drift map of eq. (28), whose increments are
+ * dr = 0 and dv = tau a_ij, a_ij = -mu X / r^3.  The step stays second order
+ * for any fixed eta; eta = 0 (the default) solves every pair by Kepler.
+ * stats: pair_solves counts the Kepler pairs, pair_kicks the kicked ones.
+ * While eta > 0, the learned starter, harvests and the other composition
+ * schemes are SAKURA_EINVAL.  EINVAL for eta < 0 or not finite. */
+int sakura_set_hybrid(sakura_t *h, double eta);
 
 /* Batched ensembles: nsys independent systems, each of 1..64 particles, stored
  * back to back (CSR): system s owns particles offsets[s] .. offsets[s+1]-1 of

@@ -33,6 +33,7 @@ struct DevCounters {
     unsigned long long dom_pairs, dom_iters; // solves in the starter network's domain
     unsigned long long learned, restarts;    // network starters used; restarts from the plain one
     unsigned defer_ntiles, defer_next;       // deferred-pair list of the current step
+    unsigned long long kicks;                // close-pair hybrid: pairs given the eq. (28) kick
 };
 
 // Iteration statistics are added into NSLOT counter slots of one cache line
@@ -45,7 +46,7 @@ struct SlotStats {
     unsigned learned, restarts;
     unsigned pad;
     unsigned long long dom_pairs, dom_iters;
-    unsigned long long pad2;
+    unsigned long long kicks;
 };
 static_assert(sizeof(SlotStats) == 64, "one cache line per slot");
 
@@ -75,6 +76,11 @@ __device__ inline void slot_add_guess(SlotStats *slots, unsigned block, const Gu
     }
     if (g.learned) atomicAdd(&sl->learned, g.learned);
     if (g.restarts) atomicAdd(&sl->restarts, g.restarts);
+}
+
+__device__ inline void slot_add_kicks(SlotStats *slots, unsigned block, unsigned long long k)
+{
+    if (k) atomicAdd(&slots[block & (NSLOT - 1)].kicks, k);
 }
 
 __device__ inline unsigned wave_sum(unsigned x)
@@ -148,6 +154,7 @@ struct sakura {
     int *defer_idx = nullptr;     // per-tile counts, then the compact tile list
     int64_t cap_defer_idx = 0;
     bool has_model = false;
+    double hybrid_eta = 0.0;      // close-pair hybrid threshold (0: every pair by Kepler)
     unsigned model_gen = 0;       // bumped by every model load (graph keys)
     kep::GuessNet net{};          // the loaded network (domain of the model)
     // harvest
@@ -223,6 +230,7 @@ inline void guess_stats(const DevCounters &c, sakura_stats *st)
     st->guess_domain_iters = c.dom_iters;
     st->guess_learned = c.learned;
     st->guess_restarts = c.restarts;
+    st->pair_kicks = c.kicks;
 }
 
 inline int status_code(unsigned st)

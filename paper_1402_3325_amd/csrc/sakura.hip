@@ -25,6 +25,7 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
     slots[t].restarts = 0;
     slots[t].dom_pairs = 0;
     slots[t].dom_iters = 0;
+    slots[t].kicks = 0;
     if (t == 0) {
         c->status = 0;
         c->iters_max = 0;
@@ -39,6 +40,7 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
         c->restarts = 0;
         c->defer_ntiles = 0;
         c->defer_next = 0;
+        c->kicks = 0;
     }
     if (t < 32) c->hist[t] = 0;
 }
@@ -73,6 +75,7 @@ __global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
     const unsigned long long dit = fold_slots(a, sl.dom_iters, false);
     const unsigned long long lrn = fold_slots(a, sl.learned, false);
     const unsigned long long rst = fold_slots(a, sl.restarts, false);
+    const unsigned long long kick = fold_slots(a, sl.kicks, false);
     if (t == 0) {
         c->pair_solves = solves;
         c->iters_total = iters;
@@ -82,6 +85,7 @@ __global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
         c->dom_iters = dit;
         c->learned = lrn;
         c->restarts = rst;
+        c->kicks = kick;
     }
 }
 
@@ -131,6 +135,18 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
     }
 }
 
+// Close-pair test of the hybrid step: the step is not small against the pair's
+// own time scales, t sqrt(mu / r^3) > eta or t |W| / r > eta, evaluated without
+// square roots as (t^2 mu)^2 > eta^4 r2^3 or t^2 w2 > eta^2 r2, with r2 and w2
+// formed as fma(x, x, fma(y, y, z z)) and every product rounded in the order
+// written, so the decision is a fixed function of X, W, t, mu and eta.
+__device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, double e2,
+                                    double e4)
+{
+    const double A = t2 * mu;
+    return (A * A > e4 * ((r2 * r2) * r2)) | (t2 * w2 > e2 * r2);
+}
+
 // All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
 //
 // Lane l holds particle i = 64 I + l and its i-side sums in registers; block
@@ -152,10 +168,15 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
 // MODE selects the starter: 0 plain; with a loaded network 1 plain with
 // domain statistics, 3 plain with harvest rows, 4 pairs that may lie in the
 // network's domain listed for k_deferred (which starts those in the domain
-// from the network) and the rest solved plainly.
+// from the network) and the rest solved plainly.  MODE 5 is the close-pair
+// hybrid: close pairs (hybrid_close, thresholds e2 = eta^2, e4 = eta^4) take
+// the plain Kepler solve, the others the drift-kick-drift map of eq. (28),
+// dr = 0 and dv = tau a_ij, and the solve runs only in sub-steps where some
+// lane of the wavefront has a close pair.
 template <bool HIST, int MODE, bool DEFKP = false>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double cb, double ca, double G,
+                                                double e2, double e4,
                                                 const double *__restrict__ S,
                                                 double *__restrict__ part,
                                                 DevCounters *cnt, SlotStats *slots,
@@ -196,6 +217,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const bool valid_i = ig < n;
     const double wgt_j = G * xi[6];
     const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
+    const double t2 = tau * tau, mtau = -tau; // MODE 5
     const int nj = n - J * TILE; // valid j slots in this block
 
     // Every lane solves a pair in every sub-step (lanes without one solve
@@ -203,6 +225,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     // are summed over all lanes and the trivial ones taken off at the end.
     unsigned info_sum = 0, info_max = 0; // per lane: sum and maximum of kep::pack_info
     unsigned long long n_solve = 0;      // per wave (ballot count)
+    unsigned long long n_kick = 0;       // per wave, MODE 5
     GuessCount gc;                       // per wave
     unsigned dom_it = 0;                 // per lane
     int room = kep::DEFER_CAP;           // MODE 4: list slots left
@@ -221,6 +244,66 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         const double msum = mi + mj;
         const bool act = valid_i && (q < nj) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
+        if constexpr (MODE == 5) {
+            const double X0 = xi[0] - sj[0][q], X1 = xi[1] - sj[1][q], X2 = xi[2] - sj[2][q];
+            const double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q], w2 = xi[5] - sj[5][q];
+            const double r2 = fma(X0, X0, fma(X1, X1, X2 * X2));
+            const double ws = fma(w0, w0, fma(w1, w1, w2 * w2));
+            const bool close = act & hybrid_close(t2, G * msum, r2, ws, e2, e4);
+            // eq. (28): the relative velocity changes by tau a_ij at X and the
+            // position increment vanishes; per unit mu, dv = -tau X / r^3
+            const bool kick = act & !close & (r2 > 0.0);
+            bool collide = act & !close & !(r2 > 0.0);
+            const double rinv = kep::rsqrt_refined(r2); // used only where kick holds
+            const double kf = kick ? mtau * (rinv * rinv * rinv) : 0.0;
+            const double wgt_i = G * mj;
+            if (!__builtin_amdgcn_ballot_w64(close)) {
+                // no close pair in this sub-step: velocity sums only, weights
+                // folded into the kick
+                const double ki = wgt_i * kf, kj = -wgt_j * kf;
+                ai[3] = fma(ki, X0, ai[3]);
+                ai[4] = fma(ki, X1, ai[4]);
+                ai[5] = fma(ki, X2, ai[5]);
+                sjs[3][q] = fma(kj, X0, sjs[3][q]);
+                sjs[4][q] = fma(kj, X1, sjs[4][q]);
+                sjs[5][q] = fma(kj, X2, sjs[5][q]);
+            } else {
+                // the Kepler map of eq. (26), as in MODE 0, for the close lanes
+                double d[6] = {0.0, 0.0, 0.0, kf * X0, kf * X1, kf * X2};
+                const double x0 = fma(-cb, w0, X0), x1 = fma(-cb, w1, X1), x2 = fma(-cb, w2, X2);
+                const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+                const bool kl = close && (r0sq > 0.0);
+                collide = collide || (close && !(r0sq > 0.0));
+                const kep::PairCoef f =
+                    DEFKP ? kep::kepler_flow_default(kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
+                                                     w2, kl ? r0sq : 1.0)
+                          : kep::kepler_flow(kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2,
+                                             kl ? r0sq : 1.0, kp);
+                if (kl) {
+                    const double a = fma(-ca, f.fdot, f.fm1);
+                    const double b = fma(-ca, f.gdm1, f.gmt);
+                    d[0] = fma(a, x0, b * w0);
+                    d[1] = fma(a, x1, b * w1);
+                    d[2] = fma(a, x2, b * w2);
+                    d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+                    d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+                    d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+                }
+                const unsigned info = kl ? (((unsigned)f.iters << 16) | f.status) : 0u;
+                info_sum += info;
+                info_max = max(info_max, info);
+                n_solve += __popcll(__builtin_amdgcn_ballot_w64(kl));
+                if (HIST && kl) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ai[c] = fma(wgt_i, d[c], ai[c]);
+                    sjs[c][q] = fma(-wgt_j, d[c], sjs[c][q]);
+                }
+            }
+            n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
+            any_collide = any_collide || __builtin_amdgcn_ballot_w64(collide) != 0;
+            continue;
+        }
         // relative state and the pair back-drift of eq. (17) by cb
         double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q],
                w2 = xi[5] - sj[5][q];
@@ -252,7 +335,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 room = room > total ? room - total : 0;
             }
         }
-        if constexpr (MODE == 0 || MODE == 4) {
+        if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
             const kep::PairCoef f =
                 DEFKP ? kep::kepler_flow_default(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
                                                  w2, live ? r0sq : 1.0)
@@ -332,16 +415,18 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         }
     }
 
-    const unsigned trivial = (unsigned)(TILE * (s1 - s0)) - (unsigned)n_solve;
+    // MODE 5 counts only the close lanes' solves
+    const unsigned trivial = MODE == 5 ? 0u : (unsigned)(TILE * (s1 - s0)) - (unsigned)n_solve;
     const unsigned it_sum = wave_sum(info_sum >> 16) - trivial;
     const unsigned it_max = n_solve ? wave_max(info_max >> 16) : 0u;
     const unsigned n_fb = wave_sum((info_sum >> 8) & 0xffu);
     const bool any_noconv = wave_sum(info_sum & 0xffu) != 0;
-    if (MODE != 0) gc.dom_iters = wave_sum(dom_it);
+    if (MODE != 0 && MODE != 5) gc.dom_iters = wave_sum(dom_it);
     const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
     if (lane == 0) {
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
-        if (MODE != 0) slot_add_guess(slots, blockIdx.x, gc);
+        if (MODE != 0 && MODE != 5) slot_add_guess(slots, blockIdx.x, gc);
+        if (MODE == 5) slot_add_kicks(slots, blockIdx.x, n_kick);
         if (flags) record_error(cnt, flags, step);
         if (MODE == 4 && room < kep::DEFER_CAP) {
             net.defer_count[blockIdx.x] = kep::DEFER_CAP - room;
@@ -633,13 +718,14 @@ __global__ void k_energy_final(int ntiles, int nblk, double G, const double *__r
 
 template <bool HIST>
 void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
-                    double cb, double ca, double G, const double *S, double *part,
+                    double cb, double ca, double G, double e2, double e4, const double *S,
+                    double *part,
                     DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
                     const kep::GuessNet &net)
 {
     // the plain solve with the default parameters built in, where they apply
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
-#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp, step, net
+#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, net
     switch (mode) {
     case 1:
         k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
@@ -653,6 +739,10 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
     case 3:
         k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         break;
+    case 5: // close-pair hybrid
+        if (defkp) k_pairs<HIST, 5, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        else k_pairs<HIST, 5><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        break;
     default:
         if (defkp) k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         else k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
@@ -661,16 +751,17 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
 }
 
 void launch_pairs(bool hist, int mode, int ntiles, hipStream_t st, int n, int nb, int np,
-                  double dt, double cb, double ca, double G, const double *S, double *part,
+                  double dt, double cb, double ca, double G, double e2, double e4,
+                  const double *S, double *part,
                   DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
                   const kep::GuessNet &net)
 {
     if (hist)
-        launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp,
-                             step, net);
+        launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+                             slots, kp, step, net);
     else
-        launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, S, part, cnt, slots, kp,
-                              step, net);
+        launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+                              slots, kp, step, net);
 }
 
 // One W stage of a composition of the step (Sec. 2.2): the pair map (flow
@@ -825,8 +916,18 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
     const int ntiles = nb * (nb + 1) / 2;
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
-    const int mode = sk::guess_mode(h, &net);
+    int mode = sk::guess_mode(h, &net);
     if (mode < 0) return sk::fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
+    const double e2 = h->hybrid_eta * h->hybrid_eta, e4 = e2 * e2;
+    if (h->hybrid_eta > 0.0) {
+        if (scheme != SAKURA_SCHEME_PSI)
+            return sk::fail(h, SAKURA_EINVAL, "the close-pair hybrid runs the merged step only");
+        if (mode == 2 || mode == 3)
+            return sk::fail(h, SAKURA_EINVAL,
+                            "the close-pair hybrid runs with the analytic starter only "
+                            "(no learned starter, no harvest)");
+        mode = 5;
+    }
     if (mode == 2) { // lists of deferred pairs
         if ((rc = sk::grow(h, &h->defer_pairs, &h->cap_defer, (int64_t)ntiles * kep::DEFER_CAP)))
             return rc;
@@ -845,7 +946,7 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
             const int64_t e = s * nstage + k;
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * e], st));
             launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, g.t, g.cb,
-                         g.ca, G, h->state, h->part, h->cnt, h->slots, kp, s, net);
+                         g.ca, G, e2, e4, h->state, h->part, h->cnt, h->slots, kp, s, net);
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * e], st));
             k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, h->state,
                                                  h->part, h->cnt, s);
@@ -888,6 +989,16 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                   int64_t nsteps, double G, void *stream, sakura_stats *stats)
 {
     return sakura_evolve_scheme(h, n, m, r, v, dt, nsteps, G, SAKURA_SCHEME_PSI, stream, stats);
+}
+
+int sakura_set_hybrid(sakura_t *h, double eta)
+{
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    if (!(eta >= 0.0) || !std::isfinite(eta))
+        return sk::fail(h, SAKURA_EINVAL, "eta must be finite and >= 0");
+    h->hybrid_eta = eta;
+    return SAKURA_OK;
 }
 
 int sakura_step(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,

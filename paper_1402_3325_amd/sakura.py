@@ -40,7 +40,7 @@ class Stats(ctypes.Structure):
                 ("call_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64),
                 ("failed_step", ctypes.c_int64), ("guess_domain_pairs", ctypes.c_uint64),
                 ("guess_domain_iters", ctypes.c_uint64), ("guess_learned", ctypes.c_uint64),
-                ("guess_restarts", ctypes.c_uint64)]
+                ("guess_restarts", ctypes.c_uint64), ("pair_kicks", ctypes.c_uint64)]
 
     def to_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "hist"}
@@ -113,6 +113,8 @@ def load_library():
                                        ctypes.c_int64, ctypes.c_double, ctypes.c_int, P,
                                        ctypes.POINTER(Stats)]
     L.sakura_evolve_scheme.restype = ctypes.c_int
+    L.sakura_set_hybrid.argtypes = [P, ctypes.c_double]
+    L.sakura_set_hybrid.restype = ctypes.c_int
     L.sakura_energy.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double), P]
     L.sakura_energy.restype = ctypes.c_int
@@ -229,6 +231,10 @@ class Sakura:
         if rc != OK:
             self._raise(rc)
         return st.to_dict() if stats else None
+
+    def set_hybrid(self, eta: float):
+        """Close-pair hybrid threshold (0: every pair by the Kepler map)."""
+        self._ok(self._lib.sakura_set_hybrid(self._h, float(eta)))
 
     def step(self, m, r, v, dt: float, G: float = 1.0, stats: bool = False):
         n = _check_state(m, r, v)

@@ -1,0 +1,147 @@
+"""The close-pair hybrid step on the GPU (sakura_set_hybrid): per step against
+the oracle's hybrid step (error metric and 1e-12 tolerance of the step parity
+tests), the number of Kepler pairs equal to the oracle's, the two limits
+(every pair close: the plain kernel bitwise; no pair close: leapfrog), and
+sampled rows of the full-size cluster."""
+import numpy as np
+import pytest
+
+from paper_1402_3325_amd import workloads
+from tests import pins
+from tests.test_gpu_parity import TOL, _cluster_rows, _dev, step_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def lib(torch):
+    from paper_1402_3325_amd.sakura import Sakura
+    h = Sakura(0)
+    yield h
+    h.close()
+
+
+def gpu_hybrid(torch, lib, m, r, v, tau, eta, nsteps=1):
+    mt, rt, vt = _dev(torch, m, r, v)
+    lib.set_hybrid(eta)
+    try:
+        st = lib.evolve(mt, rt, vt, tau, nsteps, stats=True)
+    finally:
+        lib.set_hybrid(0.0)
+    torch.cuda.synchronize()
+    return rt.cpu().numpy(), vt.cpu().numpy(), st
+
+
+def _active_pairs(m):
+    """Unordered pairs with m_i + m_j > 0 (the others exert nothing)."""
+    n = len(m)
+    nz = int(np.count_nonzero(m))
+    return n * (n - 1) // 2 - (n - nz) * (n - nz - 1) // 2
+
+
+@pytest.mark.parametrize("eta", [0.01, 0.05])
+@pytest.mark.parametrize("n", [3, 65, 333, 1000])
+def test_hybrid_parity_ragged_sizes(torch, lib, oracle, n, eta):
+    rng = np.random.default_rng(3000 + n)
+    cases = [workloads.plummer(n, rng=rng), workloads.cluster(n_stars=n - 1, rng=rng)]
+    for m, r, v, tau in cases:
+        for dt in (tau, -2.0 * tau):
+            rg, vg, st = gpu_hybrid(torch, lib, m, r, v, dt, eta)
+            ro, vo, nk = oracle.step_hybrid(m, r, v, dt, eta)
+            er, ev = step_error(rg, vg, ro, vo, r, v)
+            print(n, eta, dt, "kepler", nk, "err", er, ev)
+            assert er <= TOL and ev <= TOL, (n, eta, dt, er, ev)
+            assert st["pair_solves"] == nk
+            assert st["pair_solves"] + st["pair_kicks"] == _active_pairs(m)
+
+
+def test_hybrid_parity_plummer_4096(torch, lib, oracle):
+    m, r, v, tau, _ = workloads.config(1)
+    rg, vg, st = gpu_hybrid(torch, lib, m, r, v, tau, 0.01)
+    ro, vo, nk = oracle.step_hybrid(m, r, v, tau, 0.01)
+    er, ev = step_error(rg, vg, ro, vo, r, v)
+    print("plummer4096 hybrid: kepler", nk, "err", er, ev)
+    assert er <= TOL and ev <= TOL
+    assert st["pair_solves"] == nk and st["pair_solves"] + st["pair_kicks"] == 4096 * 4095 // 2
+
+
+def test_hybrid_cluster_16384_sampled(torch, lib, oracle):
+    """Full-size cluster (the benchmark's workload) at eta = 0.01: 3 steps,
+    each checked on sampled rows against the oracle's hybrid step."""
+    m, r, v, tau, _ = workloads.config(2)
+    rng = np.random.default_rng(17)
+    rin, vin = r, v
+    for _ in range(3):
+        rows = _cluster_rows(m, rng)
+        rg, vg, st = gpu_hybrid(torch, lib, m, rin, vin, tau, 0.01)
+        ro, vo = oracle.step_rows_hybrid(m, rin, vin, tau, 0.01, rows)
+        er, ev = step_error(rg[rows], vg[rows], ro, vo, rin[rows], vin[rows])
+        print("cluster16384 hybrid: kepler", st["pair_solves"], "kicks", st["pair_kicks"],
+              "err", er, ev)
+        assert er <= TOL and ev <= TOL
+        assert st["pair_solves"] + st["pair_kicks"] == _active_pairs(m)
+        rin, vin = rg, vg
+
+
+def test_every_pair_close_is_the_plain_kernel(torch, lib):
+    m, r, v, tau = workloads.cluster(n_stars=999, rng=np.random.default_rng(5))
+    rg, vg, st = gpu_hybrid(torch, lib, m, r, v, tau, 1e-30, nsteps=3)
+    mt, rt, vt = _dev(torch, m, r, v)
+    lib.evolve(mt, rt, vt, tau, 3)
+    torch.cuda.synchronize()
+    assert st["pair_kicks"] == 0
+    assert np.array_equal(rg, rt.cpu().numpy()) and np.array_equal(vg, vt.cpu().numpy())
+
+
+def test_no_pair_close_is_leapfrog(torch, lib):
+    """Every pair kicked: the step is the drift-kick-drift leapfrog (eq. 28
+    and its reduction), against a plain numpy leapfrog."""
+    m, r, v, _ = workloads.plummer(500, rng=np.random.default_rng(6))
+    tau = 1e-3
+    rg, vg, st = gpu_hybrid(torch, lib, m, r, v, tau, 1e30)
+    rl, vl = pins.leapfrog_dkd(m, r, v, tau)
+    er, ev = step_error(rg, vg, rl, vl, r, v)
+    assert st["pair_solves"] == 0 and st["pair_kicks"] == 500 * 499 // 2
+    assert er <= TOL and ev <= TOL, (er, ev)
+
+
+def test_massless_particles_exact_with_close_central_pairs(torch, lib):
+    """A central mass and 16383 massless particles at eta small enough that
+    every pair with the central mass is close: exact Kepler orbits; pairs of
+    massless particles exert nothing."""
+    m, r, v = workloads.test_particles(16384)
+    tau = 0.01
+    rg, vg, st = gpu_hybrid(torch, lib, m, r, v, tau, 1e-4, nsteps=2)
+    assert st["pair_solves"] == 2 * 16383 and st["pair_kicks"] == 0
+    rng = np.random.default_rng(8)
+    for i in rng.choice(np.arange(1, 16384), 100, replace=False):
+        xr, wr = pins.kepler_elements(2 * tau, m[0], r[i] - r[0], v[i] - v[0])
+        ex = float(np.max(np.abs((rg[i] - rg[0]) - xr))) / np.linalg.norm(r[i])
+        ew = float(np.max(np.abs((vg[i] - vg[0]) - wr))) / np.linalg.norm(v[i])
+        assert ex <= TOL and ew <= TOL, (i, ex, ew)
+
+
+def test_hybrid_argument_checks(torch, lib):
+    from paper_1402_3325_amd.sakura import EINVAL, SakuraError
+    m, r, v, tau = workloads.planetary(3)
+    mt, rt, vt = _dev(torch, m, r, v)
+    for eta in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(SakuraError) as e:
+            lib.set_hybrid(eta)
+        assert e.value.code == EINVAL
+    lib.set_hybrid(0.01)
+    try:
+        r0 = rt.clone()
+        with pytest.raises(SakuraError) as e:
+            lib.evolve_scheme(mt, rt, vt, tau, 1, 2)
+        assert e.value.code == EINVAL and torch.equal(rt, r0)
+    finally:
+        lib.set_hybrid(0.0)
