@@ -15,6 +15,16 @@
 // Work items (groups of systems) are sorted by cost, largest first, and popped
 // from an atomic counter by a persistent grid; every wave exits once the queue
 // is empty.
+//
+// One wavefront takes about 1.2 us per sub-step (the solve's dependency chain
+// with no other work to hide it), and a system of n particles needs about n/2
+// sequential sub-steps per step, so the largest systems set the length of
+// the launch.  Items of more than 16 lanes therefore go to workgroups of two
+// (17..32 lanes) or four (33..64) wavefronts that hold the same particles and
+// take every second or fourth sub-step, each with its own j-side LDS slots;
+// the partial sums are combined in a fixed order once per step, so all the
+// wavefronts of a group carry bitwise the same state.  The three launches run
+// as parallel branches of the captured graph.
 #include "common.hpp"
 
 #include <algorithm>
@@ -30,9 +40,12 @@ struct WorkItem {
 };
 
 // MODE selects the starter as in the tile kernel (0 plain, 1 domain
-// statistics, 2 the network's starter, 3 harvest rows).
-template <int MODE>
-__global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__restrict__ items,
+// statistics, 2 the network's starter, 3 harvest rows); WAVES (1, 2 or 4)
+// wavefronts share each item's sub-steps; DEFKP (MODE 0) calls the solve
+// with the default parameters built in.
+template <int MODE, int WAVES, bool DEFKP = false>
+__global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1))) void k_batch(int nitems,
+                                                        const WorkItem *__restrict__ items,
                                                 const int *__restrict__ order,
                                                 const int64_t *__restrict__ offsets,
                                                 const double *__restrict__ m,
@@ -42,18 +55,29 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                                                 double *__restrict__ staged, int64_t ntot,
                                                 long long nsteps,
                                                 double G, DevCounters *cnt, SlotStats *slots,
-                                                kep::KeplerParams kp, const kep::GuessNet net)
+                                                kep::KeplerParams kp, const kep::GuessNet net,
+                                                unsigned *queue)
 {
-    __shared__ double sj[7][TILE]; // x y z vx vy vz m of every lane this step
-    __shared__ double sa[6][TILE]; // j-side sums
-    const int lane = threadIdx.x;
+    __shared__ double sj[7][TILE];         // x y z vx vy vz m of every lane this step
+    __shared__ double sa[WAVES][6][TILE];  // j-side sums, per wavefront
+    __shared__ double sacc[WAVES][6][TILE]; // i-side sums, exchanged (WAVES 2)
+    __shared__ int s_item;
+    const int lane = WAVES == 1 ? (int)threadIdx.x : (int)threadIdx.x % TILE;
+    const int wv = WAVES == 1 ? 0 : (int)threadIdx.x / TILE;
     unsigned n_solve = 0, it_sum = 0, it_max = 0, n_fb = 0;
     unsigned dom_n = 0, dom_it = 0, n_learned = 0, n_restart = 0; // per lane
 
     for (;;) {
         int item = 0;
-        if (lane == 0) item = (int)atomicAdd(&cnt->work_next, 1u);
-        item = __shfl(item, 0, 64);
+        if constexpr (WAVES == 1) {
+            if (lane == 0) item = (int)atomicAdd(queue, 1u);
+            item = __shfl(item, 0, 64);
+        } else {
+            __syncthreads(); // every wavefront is done with the previous item
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+            __syncthreads();
+            item = s_item;
+        }
         if (item >= nitems) break;
         const WorkItem w = items[item];
         const int L = w.L;
@@ -86,18 +110,20 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
             double xh[3];
             for (int c = 0; c < 3; ++c) xh[c] = x[c] + h * u[c]; // (27a)
             __syncthreads(); // the previous step's readers are done
-            sj[0][lane] = xh[0];
-            sj[1][lane] = xh[1];
-            sj[2][lane] = xh[2];
-            sj[3][lane] = u[0];
-            sj[4][lane] = u[1];
-            sj[5][lane] = u[2];
-            sj[6][lane] = valid ? mi : 0.0;
-            for (int c = 0; c < 6; ++c) sa[c][lane] = 0.0;
+            if (wv == 0) {
+                sj[0][lane] = xh[0];
+                sj[1][lane] = xh[1];
+                sj[2][lane] = xh[2];
+                sj[3][lane] = u[0];
+                sj[4][lane] = u[1];
+                sj[5][lane] = u[2];
+                sj[6][lane] = valid ? mi : 0.0;
+            }
+            for (int c = 0; c < 6; ++c) sa[wv][c][lane] = 0.0;
             __syncthreads();
 
             double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int s = 1; s <= nsub; ++s) {
+            for (int s = 1 + wv; s <= nsub; s += WAVES) {
                 int ql = l + s;
                 ql = ql >= L ? ql - L : ql;
                 const int q = lane_in_tile ? g * L + ql : lane; // always inside [0, 64)
@@ -114,8 +140,11 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                 const bool live = act && !collide;
                 kep::PairFlow f;
                 if constexpr (MODE == 0) {
-                    const kep::PairCoef c = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1,
-                                                             x2, w0, w1, w2, live ? r0sq : 1.0, kp);
+                    const kep::PairCoef c =
+                        DEFKP ? kep::kepler_flow_default(live ? tau : 0.0, G * msum, x0, x1, x2,
+                                                         w0, w1, w2, live ? r0sq : 1.0)
+                              : kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
+                                                 w2, live ? r0sq : 1.0, kp);
                     f.fm1 = c.fm1;
                     f.gmt = c.gmt;
                     f.fdot = c.fdot;
@@ -152,7 +181,7 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     acc[c] = fma(wgt_i, d[c], acc[c]);
-                    sa[c][q] = fma(-wgt_j, d[c], sa[c][q]);
+                    sa[wv][c][q] = fma(-wgt_j, d[c], sa[wv][c][q]);
                 }
                 if (live) {
                     ++n_solve;
@@ -162,12 +191,36 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
                     if (!f.converged) flags |= ST_NOCONV;
                 }
                 if (collide) flags |= ST_COLLIDE;
-                __syncthreads(); // j-side sums of this sub-step visible to the next
+                // j-side sums of this sub-step visible to the next (with two
+                // wavefronts taking different numbers of sub-steps there is no
+                // workgroup barrier here: the wavefront's LDS operations complete
+                // in order, and the compiler may not move them across the fence)
+                if constexpr (WAVES == 1) __syncthreads();
+                else asm volatile("" ::: "memory");
+            }
+            double jside[6];
+            if constexpr (WAVES == 1) {
+                for (int c = 0; c < 6; ++c) jside[c] = sa[0][c][lane];
+            } else {
+                // the wavefronts' sums in a fixed order, so that all carry the
+                // same state (read only: every wavefront reads these slots)
+                for (int c = 0; c < 6; ++c) sacc[wv][c][lane] = acc[c];
+                __syncthreads();
+                for (int c = 0; c < 6; ++c) {
+                    double a = sacc[0][c][lane], j = sa[0][c][lane];
+#pragma unroll
+                    for (int w = 1; w < WAVES; ++w) {
+                        a += sacc[w][c][lane];
+                        j += sa[w][c][lane];
+                    }
+                    acc[c] = a;
+                    jside[c] = j;
+                }
             }
             bool fin = true;
             for (int c = 0; c < 3; ++c) {
-                const double rt = xh[c] + (acc[c] + sa[c][lane]);        // (27b)
-                const double v1 = u[c] + (acc[3 + c] + sa[3 + c][lane]); // (27c)
+                const double rt = xh[c] + (acc[c] + jside[c]);        // (27b)
+                const double v1 = u[c] + (acc[3 + c] + jside[3 + c]); // (27c)
                 x[c] = rt + h * v1;                                      // (27d)
                 u[c] = v1;
                 fin = fin && isfinite(x[c]) && isfinite(v1);
@@ -176,7 +229,7 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
             if (flags) record_error(cnt, flags, step);
             flags = 0;
         }
-        if (valid) {
+        if (valid && wv == 0) {
             for (int c = 0; c < 3; ++c) {
                 staged[3 * p + c] = x[c];
                 staged[3 * (ntot + p) + c] = u[c];
@@ -200,29 +253,45 @@ __global__ __launch_bounds__(TILE) void k_batch(int nitems, const WorkItem *__re
     }
 }
 
-void launch_batch(int mode, int grid, hipStream_t st, int nitems, const WorkItem *items,
-                  const int *order, const int64_t *offsets, const double *m, const double *r,
-                  const double *v, const double *dt, double *staged, int64_t ntot,
-                  long long nsteps, double G, DevCounters *cnt, SlotStats *slots,
-                  kep::KeplerParams kp, const kep::GuessNet &net)
+template <int WAVES>
+void launch_batch_w(int mode, int grid, hipStream_t st, int nitems, const WorkItem *items,
+                    const int *order, const int64_t *offsets, const double *m, const double *r,
+                    const double *v, const double *dt, double *staged, int64_t ntot,
+                    long long nsteps, double G, DevCounters *cnt, SlotStats *slots,
+                    kep::KeplerParams kp, const kep::GuessNet &net, unsigned *queue)
 {
+#define SAKURA_BATCH_ARGS nitems, items, order, offsets, m, r, v, dt, staged, ntot, nsteps, G, \
+                          cnt, slots, kp, net, queue
+    const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
     switch (mode) {
-    case 1:
-        k_batch<1><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
-                                          nsteps, G, cnt, slots, kp, net);
-        break;
-    case 2:
-        k_batch<2><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
-                                          nsteps, G, cnt, slots, kp, net);
-        break;
-    case 3:
-        k_batch<3><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
-                                          nsteps, G, cnt, slots, kp, net);
-        break;
+    case 1: k_batch<1, WAVES><<<grid, TILE * WAVES, 0, st>>>(SAKURA_BATCH_ARGS); break;
+    case 2: k_batch<2, WAVES><<<grid, TILE * WAVES, 0, st>>>(SAKURA_BATCH_ARGS); break;
+    case 3: k_batch<3, WAVES><<<grid, TILE * WAVES, 0, st>>>(SAKURA_BATCH_ARGS); break;
     default:
-        k_batch<0><<<grid, TILE, 0, st>>>(nitems, items, order, offsets, m, r, v, dt, staged, ntot,
-                                          nsteps, G, cnt, slots, kp, net);
+        if (defkp) k_batch<0, WAVES, true><<<grid, TILE * WAVES, 0, st>>>(SAKURA_BATCH_ARGS);
+        else k_batch<0, WAVES><<<grid, TILE * WAVES, 0, st>>>(SAKURA_BATCH_ARGS);
     }
+#undef SAKURA_BATCH_ARGS
+}
+
+// The three launches: the items of four, two and one wavefronts (n[0], n[1],
+// n[2] items, in that order in the item list) on st[0], st[1], st[2].
+void launch_batch(int mode, const int grid[3], const hipStream_t st[3], const int n[3],
+                  const WorkItem *items, const int *order, const int64_t *offsets,
+                  const double *m, const double *r, const double *v, const double *dt,
+                  double *staged, int64_t ntot, long long nsteps, double G, DevCounters *cnt,
+                  SlotStats *slots, kep::KeplerParams kp, const kep::GuessNet &net)
+{
+    if (n[0])
+        launch_batch_w<4>(mode, grid[0], st[0], n[0], items, order, offsets, m, r, v, dt,
+                          staged, ntot, nsteps, G, cnt, slots, kp, net, &cnt->work_next4);
+    if (n[1])
+        launch_batch_w<2>(mode, grid[1], st[1], n[1], items + n[0], order, offsets, m, r, v, dt,
+                          staged, ntot, nsteps, G, cnt, slots, kp, net, &cnt->work_next2);
+    if (n[2])
+        launch_batch_w<1>(mode, grid[2], st[2], n[2], items + n[0] + n[1], order, offsets, m,
+                          r, v, dt, staged, ntot, nsteps, G, cnt, slots, kp, net,
+                          &cnt->work_next);
 }
 
 // Staged results -> caller arrays, only when every system and step succeeded.
@@ -287,7 +356,8 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     const int64_t ntot = offsets[nsys];
 
     // Work items: systems sorted by size (largest first), equal sizes packed
-    // floor(64 / L) to a wavefront.
+    // floor(64 / L) to a wavefront; items of more than 32 lanes go to the
+    // four-wavefront launch, of 17..32 lanes to the two-wavefront one.
     std::vector<int> order((size_t)nsys);
     for (int64_t s = 0; s < nsys; ++s) order[(size_t)s] = (int)s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -309,6 +379,11 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         k = e;
     }
     const int nitems = (int)(items.size() / 4);
+    int nw[3] = {0, 0, 0}; // items of 4, 2, 1 wavefronts (sorted by L, largest first)
+    for (int k = 0; k < nitems; ++k) {
+        const int L = items[4 * k + 2];
+        ++nw[L > TILE / 2 ? 0 : (L > TILE / 4 ? 1 : 2)];
+    }
     h->host_work.assign(items.begin(), items.end());
     h->host_work.insert(h->host_work.end(), order.begin(), order.end());
 
@@ -333,7 +408,11 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
 
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
-    const int grid = std::max(1, std::min(nitems, cus * std::max(1, h->batch_waves_per_cu)));
+    const int wpc = std::max(1, h->batch_waves_per_cu);
+    const int wgrid[3] = {std::max(1, std::min(nw[0], cus * wpc / 4)),
+                          std::max(1, std::min(nw[1], cus * wpc / 2)),
+                          std::max(1, std::min(nw[2], cus * wpc))};
+    const int grid = cus * wpc; // for the graph key
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
     const int mode = guess_mode(h, &net);
@@ -362,11 +441,23 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         }
         if (!h->capture_stream)
             SAKURA_HIP(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+        for (hipStream_t *sp : {&h->capture_stream2, &h->capture_stream3})
+            if (!*sp) SAKURA_HIP(h, hipStreamCreateWithFlags(sp, hipStreamNonBlocking));
+        for (hipEvent_t *ep : {&h->graph_fork, &h->graph_join, &h->graph_join2})
+            if (!*ep) SAKURA_HIP(h, hipEventCreateWithFlags(ep, hipEventDisableTiming));
         SAKURA_HIP(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
         k_clear<<<1, NSLOT, 0, h->capture_stream>>>(h->cnt, h->slots);
-        launch_batch(mode, grid, h->capture_stream, nitems, witems, worder, h->batch_offsets, m,
-                     r, v, dt, h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp,
-                     net);
+        // the three launches as parallel branches of the graph
+        SAKURA_HIP(h, hipEventRecord(h->graph_fork, h->capture_stream));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
+        const hipStream_t bst[3] = {h->capture_stream, h->capture_stream2, h->capture_stream3};
+        launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
+                     h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
+        SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
+        SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join, 0));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join2, 0));
         k_batch_export<<<eblocks, 256, 0, h->capture_stream>>>(ntot, h->batch_state, r, v,
                                                                h->cnt);
         k_fold_stats<<<1, NSLOT, 0, h->capture_stream>>>(h->slots, h->cnt);
@@ -379,7 +470,8 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         SAKURA_HIP(h, hipGraphLaunch(h->graph_exec, st));
     } else {
         k_clear<<<1, NSLOT, 0, st>>>(h->cnt, h->slots);
-        launch_batch(mode, grid, st, nitems, witems, worder, h->batch_offsets, m, r, v, dt,
+        const hipStream_t bst[3] = {st, st, st};
+        launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
                      h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
         k_batch_export<<<eblocks, 256, 0, st>>>(ntot, h->batch_state, r, v, h->cnt);
         k_fold_stats<<<1, NSLOT, 0, st>>>(h->slots, h->cnt);

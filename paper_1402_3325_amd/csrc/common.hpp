@@ -29,7 +29,9 @@ struct DevCounters {
     unsigned long long fallbacks;
     long long failed_step;
     unsigned hist[32];
-    unsigned work_next; // work-queue head of the batched kernel
+    unsigned work_next;  // work-queue head of the batched kernel (one-wavefront items)
+    unsigned work_next2; // the same for the two-wavefront items
+    unsigned work_next4; // and for the four-wavefront items
     unsigned long long dom_pairs, dom_iters; // solves in the starter network's domain
     unsigned long long learned, restarts;    // network starters used; restarts from the plain one
     unsigned defer_ntiles, defer_next;       // deferred-pair list of the current step
@@ -139,6 +141,9 @@ struct sakura {
     int64_t cap_offsets = 0;
     std::vector<int> host_work;
     hipStream_t capture_stream = nullptr;
+    hipStream_t capture_stream2 = nullptr; // further branches of the captured batch graph
+    hipStream_t capture_stream3 = nullptr;
+    hipEvent_t graph_fork = nullptr, graph_join = nullptr, graph_join2 = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::string graph_key;

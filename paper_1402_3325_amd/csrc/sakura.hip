@@ -34,6 +34,8 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
         c->fallbacks = 0;
         c->failed_step = LLONG_MAX;
         c->work_next = 0;
+        c->work_next2 = 0;
+        c->work_next4 = 0;
         c->dom_pairs = 0;
         c->dom_iters = 0;
         c->learned = 0;
@@ -875,6 +877,11 @@ void sakura_destroy(sakura_t *h)
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    if (h->capture_stream2) (void)hipStreamDestroy(h->capture_stream2);
+    if (h->capture_stream3) (void)hipStreamDestroy(h->capture_stream3);
+    if (h->graph_fork) (void)hipEventDestroy(h->graph_fork);
+    if (h->graph_join) (void)hipEventDestroy(h->graph_join);
+    if (h->graph_join2) (void)hipEventDestroy(h->graph_join2);
     delete h;
 }
 

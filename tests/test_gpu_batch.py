@@ -114,6 +114,26 @@ def test_graph_replays_match_eager(torch, lib):
         assert np.array_equal(vt.cpu().numpy(), v_eager), rep
 
 
+def test_batch_default_parameters_match_general(torch, lib):
+    """The batched kernels built for the default solver parameters and the
+    general ones (any other max_iter) do the same arithmetic, for items of one,
+    two and four wavefronts alike."""
+    from paper_1402_3325_amd.sakura import Sakura
+    off, m, r, v, tau = small_ensemble(SIZES, seed=13)
+    hg = Sakura(0, max_iter=41)
+    try:
+        out = []
+        for h in (lib, hg):
+            h.batch_set_policy(0, 8, True)
+            mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+            st = h.batch_evolve(off, mt, rt, vt, dtt, 5, stats=True)
+            out.append((rt.cpu().numpy(), vt.cpu().numpy(), st["iters_total"]))
+    finally:
+        hg.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
 def test_batch_errors_update_nothing(torch, lib):
     from paper_1402_3325_amd.sakura import SakuraError, ENONFINITE, EINVAL
     off, m, r, v, tau = small_ensemble([5, 6, 7], seed=3)
