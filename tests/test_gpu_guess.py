@@ -261,6 +261,37 @@ def test_learned_step_matches_oracle(torch, lib, oracle):
     assert 0 < st["guess_learned"] <= st["guess_domain_pairs"]
 
 
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_learned_schemes_match_oracle(torch, lib, oracle, scheme):
+    """The learned starter inside the compositions of Sec. 2.2: the listed
+    pairs are solved by k_deferred with the stage's back-drifts (unequal in
+    the unmerged step) and its flow time (negative in the triple jump's middle
+    stage); one step against the oracle's scheme."""
+    from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
+    m, r, v = small_cluster(200)
+    tau = 1.0 / 1024
+    mu, X, W, T = kepler_problems(2000, 24)
+    F, Y, D = oracle_samples(oracle, mu, X, W, T)
+    lib.set_guess_model(make_model(np.random.default_rng(5), F, D))
+    try:
+        lib.set_guess(GUESS_LEARNED)
+        mt, rt, vt = _dev(torch, m, r, v)
+        st = lib.evolve_scheme(mt, rt, vt, tau, 1, scheme, stats=True)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_guess(GUESS_ANALYTIC)
+        lib.set_guess_model(None)
+    # a multi-stage step: the tolerance allows for the amplification of a
+    # stage's rounding by the next stages where tight binaries make the step
+    # ill-conditioned, as in the scheme parity tests
+    from tests.test_gpu_schemes import conditioned_tol
+    tol, (ro, vo) = conditioned_tol(oracle, m, r, v, tau, scheme)
+    er, ev = step_error(rt.cpu().numpy(), vt.cpu().numpy(), ro, vo, r, v)
+    print("learned scheme", scheme, "err", er, ev, "tol", tol)
+    assert er <= tol and ev <= tol, (scheme, er, ev, tol)
+    assert st["guess_domain_pairs"] > 0 and st["guess_learned"] > 0
+
+
 def test_harvest_rows_match_oracle(torch, lib, oracle):
     m, r, v = small_cluster(201, n_stars=511)
     tau = 1.0 / 2048
