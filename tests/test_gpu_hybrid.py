@@ -129,6 +129,39 @@ def test_massless_particles_exact_with_close_central_pairs(torch, lib):
         assert ex <= TOL and ew <= TOL, (i, ex, ew)
 
 
+def test_hybrid_counters_agree_with_histogram(torch):
+    """Mode 5's counters (Kepler pairs, evaluations, largest count, kicks)
+    against the per-pair histogram it fills for the Kepler pairs only, with and
+    without the histogram build, on the full-size cluster and on a sphere with
+    massless particles."""
+    from paper_1402_3325_amd.sakura import Sakura
+    m, r, v, tau = workloads.cluster()
+    m2, r2, v2, _ = workloads.plummer(333, rng=np.random.default_rng(8))
+    m2 = m2.copy()
+    m2[::7] = 0.0
+    hh, hp = Sakura(0, histogram=True), Sakura(0)
+    try:
+        for mm, rr, vv, dt, eta in ((m, r, v, tau, 0.01), (m2, r2, v2, 0.05, 0.3)):
+            out = []
+            for h in (hh, hp):
+                h.set_hybrid(eta)
+                try:
+                    out.append(h.evolve(*_dev(torch, mm, rr, vv), dt, 1, stats=True))
+                finally:
+                    h.set_hybrid(0.0)
+            st_h, st_p = out
+            hist = np.array(st_h["hist"], dtype=np.int64)
+            assert hist[0] == 0 and hist.sum() == st_h["pair_solves"] > 0
+            for k in ("pair_solves", "pair_kicks", "iters_total", "iters_max", "fallbacks"):
+                assert st_h[k] == st_p[k], k
+            assert st_h["iters_total"] == int(np.sum(np.arange(32) * hist))
+            assert st_h["iters_max"] == int(np.nonzero(hist)[0].max())
+            assert st_h["pair_solves"] + st_h["pair_kicks"] == _active_pairs(mm)
+    finally:
+        hh.close()
+        hp.close()
+
+
 def test_hybrid_argument_checks(torch, lib):
     from paper_1402_3325_amd.sakura import EINVAL, SakuraError
     m, r, v, tau = workloads.planetary(3)
