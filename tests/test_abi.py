@@ -72,3 +72,23 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_enum_constants_match_the_header():
+    """The binding's scheme, starter and status constants are the header's."""
+    text = open(sakura.HEADER).read()
+    for name, value in (("SAKURA_SCHEME_PSI", sakura.SCHEME_PSI),
+                        ("SAKURA_SCHEME_UNMERGED", sakura.SCHEME_UNMERGED),
+                        ("SAKURA_SCHEME_TRIPLE_JUMP", sakura.SCHEME_TRIPLE_JUMP),
+                        ("SAKURA_GUESS_LEARNED", sakura.GUESS_LEARNED),
+                        ("SAKURA_ENOMODEL", sakura.ENOMODEL)):
+        m = re.search(rf"\b{name}\s*=\s*(-?\d+)", text)
+        assert m and int(m.group(1)) == value, name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout
