@@ -71,7 +71,9 @@ typedef struct {
     uint64_t fallbacks;    /* solves that needed a bisection or bracket-expansion step */
     uint32_t iters_max;    /* largest iteration count of one solve */
     uint32_t hist[32];     /* solves by iteration count (bin 31 holds >= 31); opts.histogram */
-    double pair_kernel_ms; /* summed duration of the pair-kernel launches (HIP events) */
+    double pair_kernel_ms; /* summed duration of the pair-kernel launches (HIP events; a
+                              call holds at most 256 launches' events: each pair is read
+                              back, waiting for its launch, before it is reused) */
     double call_ms;        /* duration of the whole call on the stream (HIP events) */
     int64_t pair_launches; /* number of pair-kernel launches */
     int64_t failed_step;   /* first failing step, -1 if none */

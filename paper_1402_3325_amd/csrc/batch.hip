@@ -422,13 +422,17 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     const unsigned eblocks = (unsigned)((3 * ntot + 255) / 256);
 
     // The launch sequence is captured once into a graph (on a private stream)
-    // and replayed while the arguments stay the same.
-    char keybuf[512];
-    std::snprintf(keybuf, sizeof(keybuf), "%p %p %p %p %p %p %lld %lld %a %d %d %a %d %d %u %p %lld %a %a %a %a",
+    // and replayed while every argument baked into it stays the same: the
+    // pointers, the particle count (state layout, export size) and the item
+    // split over the three launch widths (their grids and item ranges).
+    char keybuf[640];
+    std::snprintf(keybuf, sizeof(keybuf),
+                  "%p %p %p %p %p %p %p %lld %lld %lld %a %d %d %d %d %d %a %d %d %u %p %lld %a %a %a %a",
                   (const void *)m, (void *)r, (void *)v, (const void *)dt,
-                  (void *)h->batch_state, (void *)h->batch_work, (long long)nsys,
-                  (long long)nsteps, G, nitems, grid, kp.tol, kp.max_iter, mode, h->model_gen,
-                  (void *)net.rows, net.row_cap, net.tau2_lo, net.tau2_hi, net.b_lo, net.e2_hi);
+                  (void *)h->batch_state, (void *)h->batch_work, (void *)h->batch_offsets,
+                  (long long)nsys, (long long)ntot, (long long)nsteps, G, nitems, nw[0], nw[1],
+                  nw[2], grid, kp.tol, kp.max_iter, mode, h->model_gen, (void *)net.rows,
+                  net.row_cap, net.tau2_lo, net.tau2_hi, net.b_lo, net.e2_hi);
     const bool use_graph = !h->batch_no_graph;
     if (use_graph && (h->graph_exec == nullptr || h->graph_key != keybuf)) {
         if (h->graph_exec) {
@@ -445,23 +449,38 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
             if (!*sp) SAKURA_HIP(h, hipStreamCreateWithFlags(sp, hipStreamNonBlocking));
         for (hipEvent_t *ep : {&h->graph_fork, &h->graph_join, &h->graph_join2})
             if (!*ep) SAKURA_HIP(h, hipEventCreateWithFlags(ep, hipEventDisableTiming));
+        // recorded by a function so that a failed record still ends the
+        // capture (the stream would otherwise stay in capture mode)
+        auto record = [&]() -> int {
+            k_clear<<<1, NSLOT, 0, h->capture_stream>>>(h->cnt, h->slots);
+            // the three launches as parallel branches of the graph
+            SAKURA_HIP(h, hipEventRecord(h->graph_fork, h->capture_stream));
+            SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
+            SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
+            const hipStream_t bst[3] = {h->capture_stream, h->capture_stream2, h->capture_stream3};
+            launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
+                         h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
+            SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
+            SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
+            SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join, 0));
+            SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join2, 0));
+            k_batch_export<<<eblocks, 256, 0, h->capture_stream>>>(ntot, h->batch_state, r,
+                                                                   v, h->cnt);
+            k_fold_stats<<<1, NSLOT, 0, h->capture_stream>>>(h->slots, h->cnt);
+            SAKURA_HIP(h, hipGetLastError());
+            return SAKURA_OK;
+        };
         SAKURA_HIP(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
-        k_clear<<<1, NSLOT, 0, h->capture_stream>>>(h->cnt, h->slots);
-        // the three launches as parallel branches of the graph
-        SAKURA_HIP(h, hipEventRecord(h->graph_fork, h->capture_stream));
-        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
-        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
-        const hipStream_t bst[3] = {h->capture_stream, h->capture_stream2, h->capture_stream3};
-        launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
-                     h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
-        SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
-        SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
-        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join, 0));
-        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream, h->graph_join2, 0));
-        k_batch_export<<<eblocks, 256, 0, h->capture_stream>>>(ntot, h->batch_state, r, v,
-                                                               h->cnt);
-        k_fold_stats<<<1, NSLOT, 0, h->capture_stream>>>(h->slots, h->cnt);
-        SAKURA_HIP(h, hipStreamEndCapture(h->capture_stream, &h->graph));
+        const int crc = record();
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(h->capture_stream, &g);
+        if (crc || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            h->graph_key.clear();
+            return crc ? crc : fail(h, SAKURA_EHIP, std::string("hipStreamEndCapture: ") +
+                                                        hipGetErrorString(ee));
+        }
+        h->graph = g;
         SAKURA_HIP(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
         h->graph_key = keybuf;
     }

@@ -809,6 +809,19 @@ int scheme_stages(int scheme, double dt, Stage st[3], int &count, double &first)
     }
 }
 
+// event pairs that time the pair launches of one evolve call
+constexpr int64_t TIMING_RING = 256;
+
+// adds the duration of the launch bracketed by event pair `slot` (waits for it)
+int read_pair_timing(sakura_t *h, size_t slot, double *total_ms)
+{
+    float ms = 0.0f;
+    SAKURA_HIP(h, hipEventSynchronize(h->events[3 + 2 * slot]));
+    SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[2 + 2 * slot], h->events[3 + 2 * slot]));
+    *total_ms += ms;
+    return SAKURA_OK;
+}
+
 int need_events(sakura_t *h, size_t count)
 {
     while (h->events.size() < count) {
@@ -918,7 +931,12 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
     if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE))) return rc;
     const bool timing = stats != nullptr;
     const int64_t nlaunch = nsteps * nstage;
-    if (timing && (rc = need_events(h, 2 + 2 * (size_t)nlaunch))) return rc;
+    // pair launches are timed with a ring of event pairs: a pair is read back
+    // (waiting for the launch it bracketed) before it is recorded again, so a
+    // long evolve holds at most TIMING_RING launches' events
+    const int64_t ring = std::min<int64_t>(nlaunch, TIMING_RING);
+    if (timing && (rc = need_events(h, 2 + 2 * (size_t)ring))) return rc;
+    double pair_ms = 0.0;
 
     const int ntiles = nb * (nb + 1) / 2;
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
@@ -951,10 +969,12 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
         for (int k = 0; k < nstage; ++k) {
             const Stage &g = stages[k];
             const int64_t e = s * nstage + k;
-            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * e], st));
+            const size_t slot = timing ? (size_t)(e % ring) : 0;
+            if (timing && e >= ring && (rc = read_pair_timing(h, slot, &pair_ms))) return rc;
+            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * slot], st));
             launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, g.t, g.cb,
                          g.ca, G, e2, e4, h->state, h->part, h->cnt, h->slots, kp, s, net);
-            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * e], st));
+            if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * slot], st));
             k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, h->state,
                                                  h->part, h->cnt, s);
         }
@@ -976,13 +996,10 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
         for (int k = 0; k < 32; ++k) stats->hist[k] = c.hist[k];
         stats->pair_launches = nlaunch;
         stats->failed_step = c.status ? c.failed_step : -1;
+        for (int64_t k = 0; k < ring; ++k)
+            if ((rc = read_pair_timing(h, (size_t)k, &pair_ms))) return rc;
+        stats->pair_kernel_ms = pair_ms;
         float ms = 0.0f;
-        double tot = 0.0;
-        for (int64_t e = 0; e < nlaunch; ++e) {
-            SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[2 + 2 * e], h->events[3 + 2 * e]));
-            tot += ms;
-        }
-        stats->pair_kernel_ms = tot;
         SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
         stats->call_ms = ms;
     }

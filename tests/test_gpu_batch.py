@@ -173,3 +173,32 @@ def test_ensemble_4096_sampled_systems(torch, lib, oracle):
         ro, vo = oracle.step(m[a:b], r[a:b], v[a:b], tau[s])
         er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
         assert er <= TOL and ev <= TOL, (s, sizes[s], er, ev)
+
+
+def test_graph_follows_a_new_ensemble_in_the_same_buffers(torch, lib):
+    """Two ensembles with the same number of systems and of work items but
+    different particle counts and launch widths ([40, 40]: two items for the
+    four-wavefront launch; [30, 20]: two for the two-wavefront one), evolved
+    one after the other in the same device buffers: the second call must
+    capture a new graph, and equals the same call on a fresh handle."""
+    from paper_1402_3325_amd.sakura import Sakura
+    lib.batch_set_policy(0, 8, True)
+    offa, ma, ra, va, ta = small_ensemble([40, 40], seed=41)
+    offb, mb, rb, vb, tb = small_ensemble([30, 20], seed=42)
+    mt, rt, vt, dtt = _dev(torch, ma, ra, va, ta)
+    lib.batch_evolve(offa, mt, rt, vt, dtt, 3)
+    nb = int(offb[-1])
+    mt[:nb].copy_(torch.from_numpy(mb))
+    rt[:nb].copy_(torch.from_numpy(rb))
+    vt[:nb].copy_(torch.from_numpy(vb))
+    dtt.copy_(torch.from_numpy(tb))
+    lib.batch_evolve(offb, mt[:nb], rt[:nb], vt[:nb], dtt, 3)
+    fresh = Sakura(0)
+    try:
+        m2, r2, v2, d2 = _dev(torch, mb, rb, vb, tb)
+        fresh.batch_evolve(offb, m2, r2, v2, d2, 3)
+    finally:
+        fresh.close()
+    torch.cuda.synchronize()
+    assert np.array_equal(rt[:nb].cpu().numpy(), r2.cpu().numpy())
+    assert np.array_equal(vt[:nb].cpu().numpy(), v2.cpu().numpy())

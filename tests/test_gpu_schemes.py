@@ -185,3 +185,17 @@ def test_unknown_scheme_is_rejected(torch, lib):
         lib.evolve_scheme(mt, rt, vt, tau, 1, 7)
     assert e.value.code == EINVAL
     assert torch.equal(rt, r0)
+
+
+@pytest.mark.parametrize("scheme,nsteps", [("psi", 300), ("triple_jump", 200)])
+def test_launch_timing_over_many_launches(torch, lib, scheme, nsteps):
+    """More pair launches in one call than the ring of timing events holds
+    (256): every launch is counted, the summed pair-kernel time is positive and
+    within the call's, and timing leaves the results bitwise unchanged."""
+    m, r, v, tau = workloads.planetary(65, rng=np.random.default_rng(31))
+    rs, vs, st = gpu_scheme(torch, lib, m, r, v, tau, scheme, nsteps=nsteps, stats=True)
+    rq, vq, _ = gpu_scheme(torch, lib, m, r, v, tau, scheme, nsteps=nsteps)
+    assert st["pair_launches"] == nsteps * SCHEMES[scheme][1]
+    assert 0.0 < st["pair_kernel_ms"] <= st["call_ms"]
+    assert st["failed_step"] == -1
+    assert np.array_equal(rs, rq) and np.array_equal(vs, vq)
