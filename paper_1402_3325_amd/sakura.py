@@ -199,6 +199,13 @@ class Sakura:
         msg = self._lib.sakura_last_error(self._h)
         raise SakuraError(rc, msg.decode() if msg else "")
 
+    def _state(self, m, r, v):
+        n = _check_state(m, r, v)
+        if m.device.index != self.device:
+            raise ValueError(f"m, r, v are on {m.device}; the handle is bound to "
+                             f"cuda:{self.device}")
+        return n
+
     @staticmethod
     def _stream(t):
         import torch
@@ -207,7 +214,7 @@ class Sakura:
     def evolve(self, m, r, v, dt: float, nsteps: int, G: float = 1.0, stats: bool = False):
         """nsteps steps of eqs. (27a-d); r, v updated in place.  Returns the
         stats dict when stats=True."""
-        n = _check_state(m, r, v)
+        n = self._state(m, r, v)
         st = Stats()
         rc = self._lib.sakura_evolve(self._h, n, ctypes.c_void_p(m.data_ptr()),
                                      ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
@@ -221,7 +228,7 @@ class Sakura:
                       stats: bool = False):
         """nsteps steps of a composition of the step (SCHEME_PSI, SCHEME_UNMERGED,
         SCHEME_TRIPLE_JUMP); r, v updated in place."""
-        n = _check_state(m, r, v)
+        n = self._state(m, r, v)
         st = Stats()
         rc = self._lib.sakura_evolve_scheme(self._h, n, ctypes.c_void_p(m.data_ptr()),
                                             ctypes.c_void_p(r.data_ptr()),
@@ -237,7 +244,7 @@ class Sakura:
         self._ok(self._lib.sakura_set_hybrid(self._h, float(eta)))
 
     def step(self, m, r, v, dt: float, G: float = 1.0, stats: bool = False):
-        n = _check_state(m, r, v)
+        n = self._state(m, r, v)
         st = Stats()
         rc = self._lib.sakura_step(self._h, n, ctypes.c_void_p(m.data_ptr()),
                                    ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
@@ -252,12 +259,13 @@ class Sakura:
         import torch
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         nsys = off.shape[0] - 1
-        n = _check_state(m, r, v)
+        n = self._state(m, r, v)
         if nsys < 1 or off[0] != 0 or off[-1] != n:
             raise ValueError("offsets must start at 0 and end at len(m)")
         if not (isinstance(dt, torch.Tensor) and dt.dtype == torch.float64 and dt.is_cuda
-                and dt.is_contiguous() and tuple(dt.shape) == (nsys,)):
-            raise TypeError("dt must be a contiguous float64 CUDA tensor of shape [nsys]")
+                and dt.device == m.device and dt.is_contiguous() and tuple(dt.shape) == (nsys,)):
+            raise TypeError("dt must be a contiguous float64 CUDA tensor of shape [nsys] "
+                            "on the device of m")
         return off, nsys
 
     def batch_evolve(self, offsets, m, r, v, dt, nsteps: int, G: float = 1.0, stats: bool = False):
@@ -295,7 +303,7 @@ class Sakura:
 
     def energy(self, m, r, v, G: float = 1.0):
         """{E, K, U, P, L, Rcm} of eqs. (1-3), computed on the GPU."""
-        n = _check_state(m, r, v)
+        n = self._state(m, r, v)
         out = (ctypes.c_double * 12)()
         rc = self._lib.sakura_energy(self._h, n, ctypes.c_void_p(m.data_ptr()),
                                      ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
