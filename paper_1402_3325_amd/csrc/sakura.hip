@@ -688,23 +688,49 @@ __global__ __launch_bounds__(TILE) void k_energy_bodies(int n, const double *__r
     }
 }
 
-// Compensated, fixed-order totals: out = {E, K, U, P[3], L[3], Rcm[3]}.
-__global__ void k_energy_final(int ntiles, int nblk, double G, const double *__restrict__ tile_u,
-                               const double *__restrict__ blk, double *__restrict__ out)
+// compensated sum (s, e) of a sequence: TwoSum of each term into s, its
+// rounding error into e
+__device__ __forceinline__ void two_sum_add(double &s, double &e, double x)
 {
-    const int k = threadIdx.x; // 0 -> U, 1..11 -> body sums, others idle
-    double s = 0.0, e = 0.0;
-    const int cnt = (k == 0) ? ntiles : (k < 12 ? nblk : 0);
-    for (int t = 0; t < cnt; ++t) {
-        const double x = (k == 0) ? tile_u[t] : blk[(size_t)t * 11 + (k - 1)];
-        const double y = s + x;
-        const double bp = y - s;
-        e += (s - (y - bp)) + (x - bp);
-        s = y;
-    }
+    const double y = s + x;
+    const double bp = y - s;
+    e += (s - (y - bp)) + (x - bp);
+    s = y;
+}
+
+// Compensated, fixed-order totals: out = {E, K, U, P[3], L[3], Rcm[3]}.
+// Final sums of the energy diagnostics: the tile potentials (component 0) and
+// the 11 per-block body sums (components 1..11).  Each of the 256 threads
+// takes a strided share of a component with TwoSum, and the 256 (s, e) pairs
+// are combined in a fixed binary tree, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_energy_final(int ntiles, int nblk, double G,
+                                                      const double *__restrict__ tile_u,
+                                                      const double *__restrict__ blk,
+                                                      double *__restrict__ out)
+{
+    __shared__ double ps[256], pe[256];
     __shared__ double tot[12];
-    if (k < 12) tot[k] = s + e;
-    __syncthreads();
+    const int k = threadIdx.x;
+    for (int c = 0; c < 12; ++c) {
+        const int cnt = c == 0 ? ntiles : nblk;
+        double s = 0.0, e = 0.0;
+        for (int t = k; t < cnt; t += 256)
+            two_sum_add(s, e, c == 0 ? tile_u[t] : blk[(size_t)t * 11 + (c - 1)]);
+        ps[k] = s;
+        pe[k] = e;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (k < w) {
+                double s2 = ps[k], e2 = pe[k] + pe[k + w];
+                two_sum_add(s2, e2, ps[k + w]);
+                ps[k] = s2;
+                pe[k] = e2;
+            }
+            __syncthreads();
+        }
+        if (k == 0) tot[c] = ps[0] + pe[0];
+        __syncthreads();
+    }
     if (k == 0) {
         const double U = -G * tot[0], K = tot[1], M = tot[2];
         out[0] = K + U;
@@ -1048,7 +1074,7 @@ int sakura_energy(sakura_t *h, int64_t n, const double *m, const double *r, cons
     double *tile_u = h->scratch_e, *blk = tile_u + ntiles, *dout = blk + 11 * (size_t)nb;
     k_energy_pairs<<<ntiles, sk::TILE, 0, st>>>((int)n, nb, m, r, tile_u);
     k_energy_bodies<<<nb, sk::TILE, 0, st>>>((int)n, m, r, v, blk);
-    k_energy_final<<<1, 64, 0, st>>>(ntiles, nb, G, tile_u, blk, dout);
+    k_energy_final<<<1, 256, 0, st>>>(ntiles, nb, G, tile_u, blk, dout);
     SAKURA_HIP(h, hipGetLastError());
     SAKURA_HIP(h, hipMemcpyAsync(h->host_out, dout, 12 * sizeof(double), hipMemcpyDeviceToHost, st));
     SAKURA_HIP(h, hipStreamSynchronize(st));

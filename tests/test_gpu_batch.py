@@ -202,3 +202,11 @@ def test_graph_follows_a_new_ensemble_in_the_same_buffers(torch, lib):
     torch.cuda.synchronize()
     assert np.array_equal(rt[:nb].cpu().numpy(), r2.cpu().numpy())
     assert np.array_equal(vt[:nb].cpu().numpy(), v2.cpu().numpy())
+
+
+def test_batch_step_sizes_must_be_on_the_device(torch, lib):
+    off, m, r, v, tau = small_ensemble([5, 3])
+    mt, rt, vt = _dev(torch, m, r, v)
+    with pytest.raises(TypeError):
+        lib.batch_evolve(off, mt, rt, vt, torch.tensor(tau, dtype=torch.float64), 1)
+    assert np.array_equal(rt.cpu().numpy(), r)

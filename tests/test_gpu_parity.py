@@ -201,7 +201,7 @@ def test_errors_leave_state_unchanged(torch, lib):
 
 
 def test_energy_matches_oracle(torch, lib, oracle):
-    for k in (0, 1):
+    for k in (0, 1, 2):
         m, r, v, tau, _ = workloads.config(k)
         mt, rt, vt = _dev(torch, m, r, v)
         eg = lib.energy(mt, rt, vt)
