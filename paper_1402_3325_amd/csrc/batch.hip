@@ -544,19 +544,33 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
     double best = 1e300;
     int best_policy = 0, best_waves = 8;
     const int keep_graph = !h->batch_no_graph;
+    // a failed probe leaves the handle's batch settings as they were
+    int saved_group[TILE + 1];
+    std::memcpy(saved_group, h->batch_group, sizeof(saved_group));
+    const int saved_waves = h->batch_waves_per_cu;
+    auto restore = [&](int code) {
+        std::memcpy(h->batch_group, saved_group, sizeof(saved_group));
+        h->batch_waves_per_cu = saved_waves;
+        h->batch_no_graph = !keep_graph;
+        return code;
+    };
     for (int policy = 0; policy < 3; ++policy) {
         for (int wi = 0; wi < 3; ++wi) {
             sakura_batch_set_policy(h, policy, waves[wi], 0);
             double t = 0.0;
             for (int rep = 0; rep < 2; ++rep) { // first run warms up
-                SAKURA_HIP(h, hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
-                                             hipMemcpyDeviceToDevice, st));
-                SAKURA_HIP(h, hipMemcpyAsync(h->tune_rv + 3 * ntot, v, 3 * ntot * sizeof(double),
-                                             hipMemcpyDeviceToDevice, st));
+                hipError_t e = hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
+                                              hipMemcpyDeviceToDevice, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(h->tune_rv + 3 * ntot, v, 3 * ntot * sizeof(double),
+                                       hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess)
+                    return restore(fail(h, SAKURA_EHIP, std::string("hipMemcpyAsync: ") +
+                                                            hipGetErrorString(e)));
                 sakura_stats s;
                 rc = sakura_batch_evolve(h, nsys, offsets, m, h->tune_rv, h->tune_rv + 3 * ntot,
                                          dt, probe_steps, G, stream, &s);
-                if (rc) return rc;
+                if (rc) return restore(rc);
                 t = s.call_ms;
             }
             if (t < best) {

@@ -210,3 +210,31 @@ def test_batch_step_sizes_must_be_on_the_device(torch, lib):
     with pytest.raises(TypeError):
         lib.batch_evolve(off, mt, rt, vt, torch.tensor(tau, dtype=torch.float64), 1)
     assert np.array_equal(rt.cpu().numpy(), r)
+
+
+def test_failed_autotune_keeps_the_settings(torch):
+    """An autotune whose probe fails (a non-finite input) leaves the handle's
+    packing policy, grid size and graph use as they were: the next evolve
+    equals that of a handle with the same settings, bitwise (odd sizes, where
+    the power-of-two policy changes the lane grouping)."""
+    from paper_1402_3325_amd.sakura import Sakura, SakuraError, ENONFINITE
+    off, m, r, v, tau = small_ensemble([5, 7, 9, 13], seed=51)
+    rb = r.copy()
+    rb[3, 1] = np.nan
+    ha, hb = Sakura(0), Sakura(0)
+    try:
+        for h in (ha, hb):
+            h.batch_set_policy(2, 16, True)
+        mt, rt, vt, dtt = _dev(torch, m, rb, v, tau)
+        with pytest.raises(SakuraError) as e:
+            ha.autotune_batch(off, mt, rt, vt, dtt)
+        assert e.value.code == ENONFINITE
+        out = []
+        for h in (ha, hb):
+            mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+            h.batch_evolve(off, mt, rt, vt, dtt, 5)
+            out.append((rt.cpu().numpy(), vt.cpu().numpy()))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    finally:
+        ha.close()
+        hb.close()
