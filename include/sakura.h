@@ -156,8 +156,10 @@ int sakura_set_hybrid(sakura_t *h, double eta);
  * m, r, v.  offsets is a HOST array of nsys + 1 entries with offsets[0] = 0;
  * dt is a DEVICE array of nsys per-system steps.  Every system takes nsteps
  * steps of eqs. (27a-d) inside one persistent kernel (the launch sequence is
- * captured in a hipGraph and replayed while the arguments are unchanged).
- * Systems do not interact.  On any error no system is updated. */
+ * captured in a hipGraph and replayed while the pointers, the counts of
+ * systems, particles, steps and work items and the solver settings are
+ * unchanged; any other call captures it again).  Systems do not interact.
+ * On any error no system is updated. */
 int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
                         double *r, double *v, const double *dt, int64_t nsteps, double G,
                         void *stream, sakura_stats *stats);
@@ -172,7 +174,8 @@ int sakura_batch_set_group(sakura_t *h, int n, int lanes);
 
 /* Time every packing policy and grid size on this ensemble for probe_steps
  * steps (on scratch copies; r and v are not modified), keep the fastest on the
- * handle and report its time in *best_ms (may be NULL). */
+ * handle and report its time in *best_ms (may be NULL).  If a probe fails,
+ * its error is returned and the handle keeps the settings it had. */
 int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
                           const double *r, const double *v, const double *dt,
                           int64_t probe_steps, double G, void *stream, double *best_ms);
