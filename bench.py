@@ -24,18 +24,22 @@ sys.path.insert(0, ROOT)
 METRIC = "Kepler pair-solves/s at N=16384 (FP64), learned-guess vs plain at 1e-12 error"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
-# Algorithmic FP64 operations per pair solve, counted in the kernel source
-# (add/sub/mul and the hardware reciprocal / reciprocal-square-root estimates
-# = 1, fma = 2) along the path almost every pair takes (one evaluation of the
-# Kepler equation in the cheapest tier, accepted with a first-order shift of
-# the G-functions, its error bound implied by the starter's small
-# corrections): pair set-up and back-drift 19, Kepler set-up, starter and tier
-# choice 42, the evaluation with its Halley step, convergence and acceptance
-# tests and shift 57, Lagrange coefficients 12, increments, weights and the
-# two-sided sums 47; every further evaluation (general Stumpff series,
-# Laguerre step and its tests) 92.
-FLOPS_FIRST = 19 + 42 + 57 + 12 + 47
-FLOPS_PER_EXTRA_ITER = 92
+# Algorithmic FP64 work per pair solve, the model of the method's cost (fma
+# counted as 2): set-up, starter, coefficients, increments and the two-sided
+# compensated sums 160 flops, and 70 flops per evaluation of the Kepler
+# equation (Stumpff series, residual and derivatives, Laguerre step), so
+# F_pair = 160 + 70 k with k the mean number of evaluations per solve, which
+# the kernel counts.  `achieved` in the roofline is F_pair x N(N-1)/2 per
+# launch over the launch's duration.
+FLOPS_SETUP = 160
+FLOPS_PER_ITER = 70
+# The same work counted in the kernel source along the path almost every pair
+# takes (one evaluation in the cheapest tier, accepted by its error bound):
+# pair set-up and back-drift 19, Kepler set-up, starter and tier choice 42, the
+# evaluation with its Halley step, tests and shift 57, Lagrange coefficients
+# 12, increments, weights and the two-sided sums 47; 92 per further evaluation.
+KERNEL_FLOPS_FIRST = 19 + 42 + 57 + 12 + 47
+KERNEL_FLOPS_PER_EXTRA_ITER = 92
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
                   "paper_1402_3325_amd/csrc/common.hpp",
@@ -44,6 +48,7 @@ KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
 # plain starter needs three or more Kepler evaluations for)
 GUESS_DOMAIN = [0.25, 64.0, -1.0, 3.0]
 LEARNED_REPEATS = 3  # alternating plain / learned timed runs in the learned comparison
+PLUMMER_HARVEST_STEPS = 2000  # harvest steps of the independent N = 4096 Plummer sphere
 TRAFFIC_FILE = "profiles/k_pairs_cluster16384.traffic.json"
 
 
@@ -69,21 +74,28 @@ def measured_profile():
 
 
 def flops_per_pair(mean_iters):
-    return FLOPS_FIRST + FLOPS_PER_EXTRA_ITER * max(mean_iters - 1.0, 0.0)
+    """The method's algorithmic flops per pair solve (model above)."""
+    return FLOPS_SETUP + FLOPS_PER_ITER * mean_iters
 
 
-def parity_sample(lib, torch, m, r, v, tau, rows):
-    """One GPU step vs the oracle on sampled rows (per-step error metric)."""
-    import oracle
-    mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
-    lib.evolve(mt, rt, vt, tau, 1)
-    rg, vg = rt.cpu().numpy()[rows], vt.cpu().numpy()[rows]
-    ro, vo = oracle.step_rows(m, r, v, tau, rows)
+def kernel_flops_per_pair(mean_iters):
+    return KERNEL_FLOPS_FIRST + KERNEL_FLOPS_PER_EXTRA_ITER * max(mean_iters - 1.0, 0.0)
+
+
+def step_error(rg, vg, ro, vo, r, v):
+    """Per-step error metric over every row: max_i |dr_i| / max(|r_i|, r_rms)
+    and the same for velocities."""
     r_rms = np.sqrt(np.mean(np.sum(r ** 2, 1)))
     v_rms = np.sqrt(np.mean(np.sum(v ** 2, 1)))
     er = np.max(np.linalg.norm(rg - ro, axis=1) / np.maximum(np.linalg.norm(ro, axis=1), r_rms))
     ev = np.max(np.linalg.norm(vg - vo, axis=1) / np.maximum(np.linalg.norm(vo, axis=1), v_rms))
     return float(er), float(ev)
+
+
+def gpu_one_step(lib, torch, m, r, v, tau):
+    mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
+    st = lib.evolve(mt, rt, vt, tau, 1, stats=True)
+    return rt.cpu().numpy(), vt.cpu().numpy(), st
 
 
 def batched(lib, torch, steps=256):
@@ -129,24 +141,31 @@ def batched(lib, torch, steps=256):
                               "tol": 1e-12}}
 
 
-def learned(torch, m, r, v, tau, steps, warmup, harvest_steps):
+def learned(torch, m, r, v, tau, steps, warmup, harvest_steps, oracle_step=None):
     """The learned Kepler starter on the same workload.  Rows are harvested
-    with the plain starter from an independent cluster (seed offset 100),
-    the network is trained by the library's own kernels, then the timed run
-    of the main workload is repeated with the network's starter.  Also
-    reports the Kepler evaluations of the pairs in the network's domain with
-    and without it, and the batched ensemble with the network."""
+    with the plain starter from independent runs of the Plummer sphere and of
+    the cluster (seed offset 100), the network is trained by the library's own
+    kernels, then the timed run of the main workload is repeated with the
+    network's starter.  Also reports, for the pairs in the network's domain,
+    the Kepler evaluations and the largest final residual of the Kepler
+    equation with and without it, the step's error against the oracle over
+    every row, and the batched ensemble with the network."""
     from paper_1402_3325_amd import workloads
     from paper_1402_3325_amd.sakura import Sakura, GUESS_ANALYTIC, GUESS_LEARNED
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     h = Sakura(0)
-    m2, r2, v2, tau2 = workloads.cluster(rng=workloads.rng_for(2, 100))
-    cap = 4_000_000
+    cap = 12_000_000
     rows = torch.zeros((cap, 12), dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
     h.harvest_begin(rows, GUESS_DOMAIN)
+    m1, r1, v1, tau1 = workloads.plummer(4096, rng=workloads.rng_for(1, 100))
+    h.evolve(dev(m1), dev(r1), dev(v1), tau1, PLUMMER_HARVEST_STEPS)
+    after_plummer = min(h.harvest_end(), cap - 1)
+    h.harvest_begin(rows[after_plummer:], GUESS_DOMAIN)
+    m2, r2, v2, tau2 = workloads.cluster(rng=workloads.rng_for(2, 100))
     h.evolve(dev(m2), dev(r2), dev(v2), tau2, harvest_steps)
-    offered = h.harvest_end()
+    offered = after_plummer + h.harvest_end()
+    torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     nrows = min(offered, cap)
     t0 = time.perf_counter()
@@ -190,8 +209,23 @@ def learned(torch, m, r, v, tau, steps, warmup, harvest_steps):
     n = len(m)
     pairs = n * (n - 1) // 2
     value = pairs * steps / wall_l
-    rows_s = np.unique(np.concatenate([[0], np.random.default_rng(12).choice(n, 63, replace=False)]))
-    er, ev = parity_sample(hl, torch, m, r, v, tau, rows_s)
+    # final residuals of the Kepler equation: one step of each starter with the
+    # diagnostic kernels (every solve evaluated once more at its root)
+    resid = {}
+    for name, guess in (("plain", GUESS_ANALYTIC), ("learned", GUESS_LEARNED)):
+        hr = Sakura(0, guess=guess, histogram=True)
+        hr.set_guess_model(model)
+        _, _, sr = gpu_one_step(hr, torch, m, r, v, tau)
+        hr.close()
+        resid[name] = {"max_rel_residual_all_solves": sr["max_rel_residual"],
+                       "domain_pairs": sr["guess_domain_pairs"],
+                       "domain_mean_iters": sr["guess_domain_iters"] /
+                       max(sr["guess_domain_pairs"], 1)}
+    parity = None
+    if oracle_step is not None:
+        rg, vg, _ = gpu_one_step(hl, torch, m, r, v, tau)
+        er, ev = step_error(rg, vg, oracle_step[0], oracle_step[1], r, v)
+        parity = {"err_r": er, "err_v": ev, "rows": int(n), "tol": 1e-12}
     out = {
         "value": value, "unit": "pair-solves/s", "vs_plain": wall_p / wall_l,
         "plain_value_interleaved": pairs * steps / wall_p,
@@ -205,11 +239,13 @@ def learned(torch, m, r, v, tau, steps, warmup, harvest_steps):
         "max_iters_plain": st_p["iters_max"], "max_iters_learned": st_l["iters_max"],
         "mean_kepler_iters": st_l["iters_total"] / max(st_l["pair_solves"], 1),
         "network_starts": st_l["guess_learned"], "restarts": st_l["guess_restarts"],
-        "training": {"harvest": f"{harvest_steps} steps of an independent N=16384 cluster "
-                                f"(seed offset 100), plain starter",
+        "final_residual": resid,
+        "training": {"harvest": f"{PLUMMER_HARVEST_STEPS} steps of an independent N=4096 "
+                                f"Plummer sphere and {harvest_steps} steps of an independent "
+                                f"N=16384 cluster (seed offset 100), plain starter",
                      "rows": int(nrows), "harvest_s": t_harvest, "fit_s": t_fit,
                      "epochs": 20, "val_mse_scaled": hist[-1]},
-        "err_vs_oracle": {"err_r": er, "err_v": ev, "rows": int(len(rows_s)), "tol": 1e-12},
+        "err_vs_oracle": parity,
     }
     hp.close()
     # the batched ensemble with the same network (few of its pairs reach the domain)
@@ -379,26 +415,55 @@ def hybrid(lib, torch, m, r, v, tau, steps, warmup, etas=(0.01, 0.03)):
     return out
 
 
-def cpu_baseline(m, r, v, tau, budget_s=15.0):
-    """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1) on
-    a bounded sample: rows of one step of the same workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(m, r, v, tau, one_core_s=4.0):
+    """The oracle (plain C, OpenMP over rows, ordered pairs as in Listing 1):
+    one full step of the same workload on every host core it is given (its
+    output is also the reference of the GPU step's error over every row), and
+    a sample of rows of that step on one core.  Each pair is solved from both
+    of its ends, as in Listing 1, so unordered pairs advance at half the
+    ordered rate."""
     import oracle
     n = len(m)
-    probe = np.arange(0, n, max(1, n // 128))
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
-    oracle.step_rows(m, r, v, tau, probe)
-    per_row = (time.perf_counter() - t0) / len(probe)
-    nrows = int(min(n, max(len(probe), budget_s / max(per_row, 1e-9))))
-    rows = np.linspace(0, n - 1, nrows).astype(np.int64)
-    t0 = time.perf_counter()
-    oracle.step_rows(m, r, v, tau, rows)
+    ro, vo = oracle.step(m, r, v, tau)
     el = time.perf_counter() - t0
-    solves = nrows * (n - 1)
-    return {"value": solves / el, "unit": "pair-solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{nrows} of {n} rows of one step of the same workload "
-                      f"({solves} ordered pair solves, each pair solved from both "
-                      f"ends as in Listing 1), {el:.2f} s"}
+    ordered = n * (n - 1)
+    # one core: rows spread over the step, sized to about one_core_s
+    oracle.set_num_threads(1)
+    try:
+        probe = np.linspace(0, n - 1, 16).astype(np.int64)
+        t1 = time.perf_counter()
+        oracle.step_rows(m, r, v, tau, probe)
+        per_row = (time.perf_counter() - t1) / len(probe)
+        nrows = int(min(n, max(16, one_core_s / max(per_row, 1e-9))))
+        rows = np.linspace(0, n - 1, nrows).astype(np.int64)
+        t1 = time.perf_counter()
+        oracle.step_rows(m, r, v, tau, rows)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(cores)
+    one = nrows * (n - 1) / el1
+    out = {"value": ordered / el / 2.0, "unit": "pair-solves/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"one full step of the same workload (all {n} rows, {ordered} ordered "
+                     f"pair solves: each of the {ordered // 2} pairs solved from both ends as "
+                     f"in Listing 1) in {el:.2f} s; value counts unordered pairs",
+           "ordered_solves_per_s": ordered / el,
+           "one_core": {"ordered_solves_per_s": one, "pair_solves_per_s": one / 2.0,
+                        "sample": f"{nrows} rows of the same step, {el1:.2f} s"},
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    return out, (ro, vo)
 
 
 def main():
@@ -414,7 +479,12 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-schemes", action="store_true")
     ap.add_argument("--no-hybrid", action="store_true")
-    ap.add_argument("--harvest-steps", type=int, default=2000)
+    # about 1e7 rows: the cluster yields ~350 rows per step in the domain
+    ap.add_argument("--harvest-steps", type=int, default=30000)
+    ap.add_argument("--clock-settle-ms", type=float, default=400.0,
+                    help="untimed steps before the warm-up, run until this long has passed "
+                         "(the pair kernel's launches speed up over the first ~30 ms of load "
+                         "while the clocks rise)")
     ap.add_argument("--accuracy", action="store_true",
                     help="only run the accuracy studies (energy error vs mass ratio and "
                          "binary hierarchy) and print their JSON line")
@@ -449,13 +519,16 @@ def main():
     pairs = n * (n - 1) // 2
     lib = Sakura(0)
 
-    parity = None
-    if not args.no_parity:
-        rows = np.unique(np.concatenate([[0], np.random.default_rng(11).choice(n, 63, replace=False)]))
-        er, ev = parity_sample(lib, torch, m, r, v, tau, rows)
-        parity = {"err_r": er, "err_v": ev, "rows": int(len(rows)), "tol": 1e-12}
-
     mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
+    # untimed: bring the clocks to their steady level on a copy of the state
+    settle_steps = 0
+    if args.clock_settle_ms > 0:
+        rs, vs = rt.clone(), vt.clone()
+        t0 = time.perf_counter()
+        while (time.perf_counter() - t0) * 1e3 < args.clock_settle_ms:
+            lib.evolve(mt, rs, vs, tau, 16)
+            settle_steps += 16
+        del rs, vs
     if args.warmup:
         lib.evolve(mt, rt, vt, tau, args.warmup)
     torch.cuda.synchronize()
@@ -470,6 +543,7 @@ def main():
     achieved = fl / (pair_ms * 1e-3) / 1e12
     prof = measured_profile()
     traffic = prof["bytes_per_launch"] if prof else None
+
 
     out = {
         "metric": METRIC,
@@ -490,23 +564,34 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic},
-        # the same roofline at the clock the counters measured during the
-        # kernel, and the FP64 work the hardware counted (null when the
-        # committed counters predate the kernel sources)
-        "roofline_at_measured_clock": ({
-            "clock_ghz": prof["clock_ghz"],
-            "peak": PEAK_FP64_TFLOPS * prof["clock_ghz"] / 2.4,
-            "frac": achieved / (PEAK_FP64_TFLOPS * prof["clock_ghz"] / 2.4),
+        "flops_per_pair": flops_per_pair(k_mean),
+        "flops_model": f"{FLOPS_SETUP} + {FLOPS_PER_ITER} k, k = mean Kepler evaluations "
+                       "per solve",
+        # the same launch against the work the kernel's source does per pair,
+        # and (from the committed counters, null once the kernel sources
+        # change) against the FP64 work the hardware counted, at 2.4 GHz and
+        # at the clock measured during the kernel
+        "roofline_kernel_count": {
+            "flops_per_pair": kernel_flops_per_pair(k_mean),
+            "frac": kernel_flops_per_pair(k_mean) * pairs / (pair_ms * 1e-3) / 1e12 /
+            PEAK_FP64_TFLOPS},
+        "roofline_hardware_counters": ({
             "hw_fp64_flops_per_pair": prof["hw_fp64_flops_per_pair"],
-            "valu_busy": prof["valu_busy"]} if prof else None),
+            "frac": prof["hw_fp64_flops_per_pair"] * pairs / (pair_ms * 1e-3) / 1e12 /
+            PEAK_FP64_TFLOPS,
+            "clock_ghz": prof["clock_ghz"],
+            "frac_at_measured_clock": prof["hw_fp64_flops_per_pair"] * pairs /
+            (pair_ms * 1e-3) / 1e12 / (PEAK_FP64_TFLOPS * prof["clock_ghz"] / 2.4),
+            "valu_busy": prof["valu_busy"],
+            "profiled_launch_ms": prof.get("launch_ms")} if prof else None),
         "pair_kernel_ms": pair_ms,
         "call_ms_events": st["call_ms"],
+        "clock_settle": {"steps": settle_steps, "ms": args.clock_settle_ms},
         "mean_kepler_iters": k_mean,
         "max_kepler_iters": st["iters_max"],
         "fallbacks": st["fallbacks"],
-        "flops_per_pair": flops_per_pair(k_mean),
         "kernel_source_hash": kernel_source_hash(),
-        "err_vs_oracle": parity,
+        "err_vs_oracle": None,
     }
     if not args.no_schemes:
         out["schemes"] = schemes(lib, torch, m, r, v, tau)
@@ -514,11 +599,24 @@ def main():
         out["hybrid"] = hybrid(lib, torch, m, r, v, tau, args.steps, args.warmup)
     if not args.no_batched:
         out["batched"] = batched(lib, torch)
+    # the oracle's full step (the CPU baseline) is the reference of the GPU
+    # step's error over every row, for the plain and the learned starter
+    cpu = None
+    oracle_step = None
+    if not args.no_cpu_baseline:
+        cpu, oracle_step = cpu_baseline(m, r, v, tau)
+    elif not args.no_parity:
+        import oracle
+        oracle_step = oracle.step(m, r, v, tau)
+    if not args.no_parity:
+        rg, vg, _ = gpu_one_step(lib, torch, m, r, v, tau)
+        er, ev = step_error(rg, vg, oracle_step[0], oracle_step[1], r, v)
+        out["err_vs_oracle"] = {"err_r": er, "err_v": ev, "rows": int(n), "tol": 1e-12}
     if not args.no_learned:
         out["learned"] = learned(torch, m, r, v, tau, args.steps, args.warmup,
-                                 args.harvest_steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, r, v, tau)
+                                 args.harvest_steps, oracle_step)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -42,7 +42,8 @@ extern "C" {
 
 enum {
     SAKURA_OK = 0,
-    SAKURA_EINVAL = -1,     /* bad argument: n < 1, dt or G not finite, G < 0, m < 0, bad offsets */
+    SAKURA_EINVAL = -1,     /* bad argument: n < 2, dt not finite, G not finite or G <= 0, m < 0,
+                               bad offsets, n beyond what one device's partial sums hold */
     SAKURA_ENONFINITE = -2, /* NaN/Inf in the input, or produced by a step */
     SAKURA_ECOLLIDE = -3,   /* two particles (after the pair back-drift) at zero separation */
     SAKURA_ENOCONV = -4,    /* a Kepler solve did not converge within max_iter */
@@ -62,7 +63,15 @@ typedef struct {
     double kepler_rtol; /* relative tolerance on the Kepler root; 0 selects 2^-50 */
     int max_iter;       /* Kepler iterations before ENOCONV; 0 selects 40; at most
                            SAKURA_MAX_ITER (sakura_create fails with EINVAL above) */
-    int histogram;      /* nonzero: fill sakura_stats.hist (one LDS atomic per pair) */
+    int histogram;      /* nonzero: diagnostic pair kernels that fill sakura_stats.hist (one
+                           LDS atomic per pair) and max_rel_residual (one more evaluation of
+                           the Kepler equation per pair) */
+    int tile_override;  /* batched ensembles: 0 packs each system size as the handle's table
+                           says (sakura_autotune_batch, sakura_batch_set_policy/_group);
+                           L in [1, 64] gives every system of n <= L particles L lanes (a
+                           64-lane tile is one wavefront per system).  The single-system
+                           pair kernel has one tile, 64 x 64 particles (the wavefront
+                           width), and ignores it.  EINVAL outside [0, 64]. */
 } sakura_opts;
 
 typedef struct {
@@ -84,6 +93,13 @@ typedef struct {
     uint64_t guess_restarts;     /* of those, searches restarted from the plain starter */
     /* Close-pair hybrid (zero unless sakura_set_hybrid is on): */
     uint64_t pair_kicks; /* pairs given the eq. (28) kick instead of a Kepler solve */
+    /* Largest relative residual |t(s) - t| / |t| of the Kepler equation at the accepted
+     * roots (t the flight time after the bound-orbit period reduction, t(s) evaluated
+     * once more at the root in FP64, stored in single precision).  Filled for every
+     * solve of the single-system paths when opts.histogram is set (except during a
+     * harvest), and for the pairs the learned starter solves in any mode; 0 otherwise
+     * (and for batched ensembles). */
+    double max_rel_residual;
 } sakura_stats;
 
 /* Create a handle on HIP device `device`; opts may be NULL (defaults).
@@ -94,8 +110,11 @@ int sakura_create(sakura_t **h, int device, const sakura_opts *opts);
 void sakura_destroy(sakura_t *h);
 
 /* One step Psi(dt), eqs. (27a-d), over all N(N-1)/2 pairs.
- * n >= 1 particles; G >= 0 the gravitational constant (the paper sets G = 1).
- * stats may be NULL (no counters, no timing). */
+ * n >= 2 particles; G > 0 the gravitational constant (the paper sets G = 1).
+ * The library keeps 0.75 n^2 bytes of partial sums (a block of 6 x 64 doubles
+ * for each side of each 64 x 64 tile, n rounded up to a multiple of 64); n
+ * whose partial sums exceed the device's memory is EINVAL, and ENOMEM is
+ * returned when an allocation fails.  stats may be NULL (no counters, no timing). */
 int sakura_step(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                 double dt, double G, void *stream, sakura_stats *stats);
 
@@ -212,11 +231,12 @@ typedef struct {
     double domain[4];                /* tau_lo, tau_hi, b_lo, e_hi */
 } sakura_guess_model;
 
-/* Load (copy, HOST pointer) or, with model = NULL, unload the network.  While
- * a model is loaded, plain-starter runs also count the solves in its domain
- * (sakura_stats.guess_domain_*).  EINVAL on non-finite values or an empty
- * domain. */
-int sakura_set_guess_model(sakura_t *h, const sakura_guess_model *model);
+/* Load or, with blob = NULL, unload the network.  blob is a HOST pointer to
+ * one sakura_guess_model, whose size bytes must equal; the library copies it
+ * and derives the bf16 inference fragments on the device from it.  While a model is loaded, plain-starter runs also count
+ * the solves in its domain (sakura_stats.guess_domain_*).  EINVAL for a wrong
+ * size, non-finite values or an empty domain. */
+int sakura_set_guess_model(sakura_t *h, const void *blob, size_t bytes);
 
 /* Starter of later calls: SAKURA_GUESS_ANALYTIC or SAKURA_GUESS_LEARNED (the
  * latter makes steps fail with ENOMODEL while no model is loaded). */

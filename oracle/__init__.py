@@ -68,6 +68,8 @@ def lib():
                                             _I64, _D, _D]
         L.sref_energy.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]
         L.sref_num_threads.restype = ctypes.c_int
+        L.sref_set_num_threads.argtypes = [ctypes.c_int]
+        L.sref_set_num_threads.restype = None
         L.sref_mlp_forward.argtypes = [_D, ctypes.c_int64, _D, _D]
         L.sref_mlp_loss_grad.argtypes = [_D, ctypes.c_int64, _D, _D, _D, _D]
         L.sref_guess_sample.argtypes = [ctypes.c_double, ctypes.c_double, _D, _D, _D, _D,
@@ -256,6 +258,11 @@ def energy(m, r, v, G=1.0):
 
 def num_threads():
     return lib().sref_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's row loops from now on (results are unchanged)."""
+    lib().sref_set_num_threads(int(n))
 
 
 MLP_PARAMS = 4801

@@ -908,3 +908,12 @@ int sref_num_threads(void)
     return 1;
 #endif
 }
+
+void sref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

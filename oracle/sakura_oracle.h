@@ -153,6 +153,9 @@ int sref_guess_sample(double tau, double mu, const double x0[3], const double w0
 /* Number of OpenMP threads the row loops use. */
 int sref_num_threads(void);
 
+/* Threads of later row loops (n > 0); the results do not depend on it. */
+void sref_set_num_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                             s_net = kep::net_starter(net, tau, cand ? G * msum : 0.0, x0, x1, x2,
                                                      w0, w1, w2, r0sq);
                     }
-                    kep::NetGuess<MODE> gp(net, (int)p, (int)(off + ql), s_net);
+                    kep::NetGuess<MODE, false> gp(net, (int)p, (int)(off + ql), s_net);
                     f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
                                          w1, w2, live ? r0sq : 1.0, kp, gp);
                     if (live && gp.in_dom) {
@@ -342,7 +342,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     if (nsys < 1 || !offsets || !m || !r || !v || !dt)
         return fail(h, SAKURA_EINVAL, "nsys < 1 or null pointer");
     if (nsys > (1 << 26)) return fail(h, SAKURA_EINVAL, "too many systems");
-    if (!std::isfinite(G) || G < 0.0) return fail(h, SAKURA_EINVAL, "G must be finite and >= 0");
+    if (!std::isfinite(G) || !(G > 0.0)) return fail(h, SAKURA_EINVAL, "G must be finite and > 0");
     if (nsteps < 0) return fail(h, SAKURA_EINVAL, "nsteps < 0");
     if (offsets[0] != 0) return fail(h, SAKURA_EINVAL, "offsets[0] must be 0");
     for (int64_t s = 0; s < nsys; ++s) {
@@ -366,7 +366,8 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     std::vector<int> items; // 4 ints per item
     for (size_t k = 0; k < order.size();) {
         const int n = (int)(offsets[order[k] + 1] - offsets[order[k]]);
-        const int L = std::max(n, std::min(TILE, h->batch_group[n]));
+        const int ov = h->opts.tile_override;
+        const int L = ov > 0 ? std::max(n, ov) : std::max(n, std::min(TILE, h->batch_group[n]));
         const int per = TILE / L;
         size_t e = k;
         while (e < order.size() && e - k < (size_t)per &&

@@ -36,6 +36,7 @@ struct DevCounters {
     unsigned long long learned, restarts;    // network starters used; restarts from the plain one
     unsigned defer_ntiles, defer_next;       // deferred-pair list of the current step
     unsigned long long kicks;                // close-pair hybrid: pairs given the eq. (28) kick
+    unsigned resid_bits;                     // largest relative Kepler residual (float bits)
 };
 
 // Iteration statistics are added into NSLOT counter slots of one cache line
@@ -46,7 +47,7 @@ struct SlotStats {
     unsigned long long pair_solves, iters_total, fallbacks;
     unsigned iters_max;
     unsigned learned, restarts;
-    unsigned pad;
+    unsigned resid_bits; // largest relative Kepler residual, as the bits of a float >= 0
     unsigned long long dom_pairs, dom_iters;
     unsigned long long kicks;
 };
@@ -83,6 +84,13 @@ __device__ inline void slot_add_guess(SlotStats *slots, unsigned block, const Gu
 __device__ inline void slot_add_kicks(SlotStats *slots, unsigned block, unsigned long long k)
 {
     if (k) atomicAdd(&slots[block & (NSLOT - 1)].kicks, k);
+}
+
+// Non-negative floats order as their bit patterns do, so the largest residual
+// is an unsigned maximum.
+__device__ inline void slot_max_resid(SlotStats *slots, unsigned block, unsigned bits)
+{
+    if (bits) atomicMax(&slots[block & (NSLOT - 1)].resid_bits, bits);
 }
 
 __device__ inline unsigned wave_sum(unsigned x)
@@ -207,6 +215,25 @@ int grow(sakura_t *h, T **buf, int64_t *cap, int64_t need)
     return SAKURA_OK;
 }
 
+// The single-system path keeps 10 np doubles of state and nb^2 blocks of
+// 6 x 64 doubles of partial sums (np = 64 nb >= n); n whose buffers exceed the
+// device's memory (or the 2^21 of the tile grid's int indexing) is EINVAL.
+inline int check_capacity(sakura_t *h, int64_t n)
+{
+    const int64_t nb = (n + TILE - 1) / TILE;
+    if (n > ((int64_t)1 << 21))
+        return fail(h, SAKURA_EINVAL, "n = " + std::to_string(n) + " exceeds 2^21");
+    const double need = (double)nb * (double)nb * 6.0 * TILE * 8.0 + 10.0 * nb * TILE * 8.0;
+    size_t total = 0;
+    if (hipDeviceTotalMem(&total, h->device) != hipSuccess) total = 0;
+    if (total && need > (double)total)
+        return fail(h, SAKURA_EINVAL,
+                    "n = " + std::to_string(n) + " needs " + std::to_string(need / 1e9) +
+                        " GB of partial sums and state; the device holds " +
+                        std::to_string((double)total / 1e9) + " GB");
+    return SAKURA_OK;
+}
+
 // Starter mode of the next launch: -1 learned requested without a model,
 // 0 plain, 1 plain with domain statistics (a model is loaded), 2 the
 // network's starter, 3 harvest.  *net receives the kernel argument.
@@ -236,6 +263,9 @@ inline void guess_stats(const DevCounters &c, sakura_stats *st)
     st->guess_learned = c.learned;
     st->guess_restarts = c.restarts;
     st->pair_kicks = c.kicks;
+    float r;
+    std::memcpy(&r, &c.resid_bits, sizeof(r));
+    st->max_rel_residual = r;
 }
 
 inline int status_code(unsigned st)

@@ -353,17 +353,24 @@ void set_domain(kep::GuessNet &g, const double d[4])
 
 extern "C" {
 
-int sakura_set_guess_model(sakura_t *h, const sakura_guess_model *model)
+int sakura_set_guess_model(sakura_t *h, const void *blob, size_t bytes)
 {
     using namespace sk;
     if (!h) return SAKURA_EINVAL;
     h->err.clear();
-    if (!model) {
+    if (!blob) {
         h->has_model = false;
         h->net = kep::GuessNet{};
         ++h->model_gen;
         return SAKURA_OK;
     }
+    if (bytes != sizeof(sakura_guess_model))
+        return fail(h, SAKURA_EINVAL, "model blob of " + std::to_string(bytes) +
+                                          " bytes; a sakura_guess_model has " +
+                                          std::to_string(sizeof(sakura_guess_model)));
+    sakura_guess_model copy;
+    std::memcpy(&copy, blob, sizeof(copy));
+    const sakura_guess_model *model = &copy;
     if (!finite_all(model->params, NPAR) || !finite_all(model->in_shift, 8) ||
         !finite_all(model->in_scale, 8) || !std::isfinite(model->out_shift) ||
         !std::isfinite(model->out_scale))

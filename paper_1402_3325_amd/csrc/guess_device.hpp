@@ -79,8 +79,10 @@ SAKURA_HD inline bool guess_domain(const GuessNet &g, double mu, double r0, doub
 #ifndef SAKURA_HOST_ONLY
 // Plain starter with domain membership (statistics of the pairs a network
 // would start), used out of line by kepler_flow_domain.
+template <bool RESID = false>
 struct DomainOnly {
     static constexpr bool active = true;
+    static constexpr bool resid = RESID;
     double tau2_lo, tau2_hi, b_lo, e2_hi;
     bool in_dom = false;
 
@@ -95,13 +97,14 @@ struct DomainOnly {
 
 // The plain flow with domain membership in the result (PairFlow::in_dom),
 // kept out of line like the plain kepler_flow; all arguments are values, so
-// the policy stays in registers.
+// the policy stays in registers.  RESID: also the residual at the root.
+template <bool RESID = false>
 __device__ __attribute__((noinline)) PairFlow
 kepler_flow_domain(double tau, double mu, double x0, double x1, double x2, double w0, double w1,
                    double w2, double r0sq, const KeplerParams &kp, double tau2_lo,
                    double tau2_hi, double b_lo, double e2_hi)
 {
-    DomainOnly pol{tau2_lo, tau2_hi, b_lo, e2_hi};
+    DomainOnly<RESID> pol{tau2_lo, tau2_hi, b_lo, e2_hi};
     PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, pol);
     f.in_dom = pol.in_dom;
     return f;
@@ -274,9 +277,12 @@ __device__ inline double net_starter(const GuessNet &g, double tau, double mu, d
 // by net_starter) for pairs in the domain; MODE 3: plain starter, and every
 // pair in the domain appends a harvest row {8 raw inputs, y = log(s r0 / t) at
 // the converged root, i, j, evaluations} (the last three as int32 bits).
-template <int MODE>
+// RESID: the flow also reports the relative residual at the root (one more
+// evaluation; the deferred pairs of the tile kernel and the evaluation kernel).
+template <int MODE, bool RESID = (MODE == 2)>
 struct NetGuess {
     static constexpr bool active = true;
+    static constexpr bool resid = RESID;
     const GuessNet &g;
     int pi, pj;          // particle indices (harvest rows)
     bool in_dom = false; // the pair lies in the network's domain

@@ -127,6 +127,7 @@ struct PairFlow {
     bool safeguarded; // a bisection or bracket-expansion step was needed
     bool restarted;   // the search was started again from the plain starter
     bool in_dom;      // kepler_flow_domain: the pair lies in the given domain
+    double resid;     // |t(s) - t| / |t| at the accepted root (policies with resid; else 0)
 };
 
 // State of the root search on t(s) = tau.
@@ -424,8 +425,11 @@ SAKURA_HD inline void initial_bracket(double t, double u, double beta, double et
 // replaced s) or START_SKIP (the pair is solved elsewhere: the flow returns
 // zero coefficients at once).  NoGuess keeps the plain starter.
 enum { START_PLAIN = 0, START_REPLACED = 1, START_SKIP = 2 };
+// A policy with resid = true also has the flow evaluate t(s) once more at the
+// accepted root (general tier) and report the relative residual.
 struct NoGuess {
     static constexpr bool active = false;
+    static constexpr bool resid = false;
     SAKURA_HD int start(double, double, double, double, double, double, double, double,
                         double, double &) { return START_PLAIN; }
     SAKURA_HD void done(double, double, double, double, double, double, double, int) {}
@@ -529,6 +533,13 @@ SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau,
     out.safeguarded = st.safeguarded;
     out.restarted = restarted;
     out.in_dom = false;
+    out.resid = 0.0;
+    if constexpr (Guess::resid) {
+        if (t != 0.0) {
+            const KepEval e = kepler_eval<0>(st.s, beta, eta, zeta, r0, t);
+            out.resid = fabs(e.F) / fabs(t);
+        }
+    }
     const double G1 = st.G1, G2 = st.G2, G3 = st.G3, r = st.r;
     out.iters = it;
     if (Guess::active) guess.done(st.s, t, mu, r0, r0inv, eta, beta, it);
@@ -561,6 +572,29 @@ SAKURA_HD __attribute__((noinline)) PairCoef kepler_flow(double tau, double mu, 
     const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
     return PairCoef{f.fm1, f.gmt, f.fdot, f.gdm1, f.iters,
                     (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u)};
+}
+// The plain flow for the diagnostic kernels: also the relative residual of
+// the Kepler equation at the accepted root.
+struct NoGuessResid : NoGuess {
+    static constexpr bool resid = true;
+};
+struct PairCoefDiag {
+    double fm1, gmt, fdot, gdm1;
+    int iters;
+    unsigned status;
+    double resid;
+};
+SAKURA_HD __attribute__((noinline)) PairCoefDiag kepler_flow_diag(double tau, double mu,
+                                                                  double x0, double x1,
+                                                                  double x2, double w0,
+                                                                  double w1, double w2,
+                                                                  double r0sq,
+                                                                  const KeplerParams &kp)
+{
+    NoGuessResid g;
+    const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    return PairCoefDiag{f.fm1, f.gmt, f.fdot, f.gdm1, f.iters,
+                        (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u), f.resid};
 }
 // The same with the default parameters built in: three fewer argument
 // registers to fill per call, and the tolerance folded into the tests.

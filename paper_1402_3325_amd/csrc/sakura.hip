@@ -26,6 +26,7 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
     slots[t].dom_pairs = 0;
     slots[t].dom_iters = 0;
     slots[t].kicks = 0;
+    slots[t].resid_bits = 0;
     if (t == 0) {
         c->status = 0;
         c->iters_max = 0;
@@ -43,6 +44,7 @@ __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
         c->defer_ntiles = 0;
         c->defer_next = 0;
         c->kicks = 0;
+        c->resid_bits = 0;
     }
     if (t < 32) c->hist[t] = 0;
 }
@@ -78,6 +80,7 @@ __global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
     const unsigned long long lrn = fold_slots(a, sl.learned, false);
     const unsigned long long rst = fold_slots(a, sl.restarts, false);
     const unsigned long long kick = fold_slots(a, sl.kicks, false);
+    const unsigned long long rb = fold_slots(a, sl.resid_bits, true);
     if (t == 0) {
         c->pair_solves = solves;
         c->iters_total = iters;
@@ -88,6 +91,7 @@ __global__ void sk::k_fold_stats(const SlotStats *slots, DevCounters *c)
         c->learned = lrn;
         c->restarts = rst;
         c->kicks = kick;
+        c->resid_bits = (unsigned)rb;
     }
 }
 
@@ -134,6 +138,26 @@ __device__ inline void tile_blocks(int t, int nb, int &I, int &J)
         I = t - j * (j - 1) / 2;
     } else {
         I = J = t - noff;
+    }
+}
+
+// The plain solve of one pair: with HIST the diagnostic copy that also
+// evaluates the Kepler equation once more at the root (relative residual);
+// otherwise the copy with the default parameters built in (DEFKP) or the
+// general one (resid 0).
+template <bool HIST, bool DEFKP>
+__device__ __forceinline__ kep::PairCoefDiag solve_pair(double t, double mu, double x0, double x1,
+                                                        double x2, double w0, double w1,
+                                                        double w2, double r0sq,
+                                                        const kep::KeplerParams &kp)
+{
+    if constexpr (HIST) {
+        return kep::kepler_flow_diag(t, mu, x0, x1, x2, w0, w1, w2, r0sq, kp);
+    } else {
+        const kep::PairCoef c =
+            DEFKP ? kep::kepler_flow_default(t, mu, x0, x1, x2, w0, w1, w2, r0sq)
+                  : kep::kepler_flow(t, mu, x0, x1, x2, w0, w1, w2, r0sq, kp);
+        return kep::PairCoefDiag{c.fm1, c.gmt, c.fdot, c.gdm1, c.iters, c.status, 0.0};
     }
 }
 
@@ -232,6 +256,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     unsigned dom_it = 0;                 // per lane
     int room = kep::DEFER_CAP;           // MODE 4: list slots left
     bool any_collide = false;
+    float rmax = 0.0f;                   // per lane, HIST: largest relative Kepler residual
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
@@ -276,11 +301,9 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
                 const bool kl = close && (r0sq > 0.0);
                 collide = collide || (close && !(r0sq > 0.0));
-                const kep::PairCoef f =
-                    DEFKP ? kep::kepler_flow_default(kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
-                                                     w2, kl ? r0sq : 1.0)
-                          : kep::kepler_flow(kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2,
-                                             kl ? r0sq : 1.0, kp);
+                const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
+                    kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, kl ? r0sq : 1.0, kp);
+                if (HIST && kl) rmax = fmaxf(rmax, (float)f.resid);
                 if (kl) {
                     const double a = fma(-ca, f.fdot, f.fm1);
                     const double b = fma(-ca, f.gdm1, f.gmt);
@@ -338,11 +361,9 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             }
         }
         if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
-            const kep::PairCoef f =
-                DEFKP ? kep::kepler_flow_default(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
-                                                 w2, live ? r0sq : 1.0)
-                      : kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2,
-                                         live ? r0sq : 1.0, kp);
+            const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
+                live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
+            if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
             const double a = fma(-ca, f.fdot, f.fm1);
             const double b = fma(-ca, f.gdm1, f.gmt);
             d[0] = fma(a, x0, b * w0);
@@ -355,9 +376,11 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         } else {
             kep::PairFlow f;
             if constexpr (MODE == 1) {
-                f = kep::kepler_flow_domain(live ? tau : 0.0, G * msum, x0, x1, x2,
-                                            w0, w1, w2, live ? r0sq : 1.0, kp, net.tau2_lo,
-                                            net.tau2_hi, net.b_lo, net.e2_hi);
+                f = kep::kepler_flow_domain<HIST>(live ? tau : 0.0, G * msum, x0, x1, x2,
+                                                  w0, w1, w2, live ? r0sq : 1.0, kp,
+                                                  net.tau2_lo, net.tau2_hi, net.b_lo,
+                                                  net.e2_hi);
+                if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
                 const bool dom = live && f.in_dom;
                 gc.dom += __popcll(__ballot(dom));
                 dom_it += dom ? (unsigned)f.iters : 0u;
@@ -425,8 +448,10 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const bool any_noconv = wave_sum(info_sum & 0xffu) != 0;
     if (MODE != 0 && MODE != 5) gc.dom_iters = wave_sum(dom_it);
     const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
+    const unsigned rbits = HIST ? wave_max(__float_as_uint(rmax)) : 0u;
     if (lane == 0) {
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+        if (HIST) slot_max_resid(slots, blockIdx.x, rbits);
         if (MODE != 0 && MODE != 5) slot_add_guess(slots, blockIdx.x, gc);
         if (MODE == 5) slot_add_kicks(slots, blockIdx.x, n_kick);
         if (flags) record_error(cnt, flags, step);
@@ -463,6 +488,7 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
     unsigned it_sum = 0, it_max = 0;
     GuessCount gc;
     bool any_noconv = false;
+    float rmax = 0.0f; // per lane: largest relative Kepler residual
     const unsigned ntl = cnt->defer_ntiles;
     for (;;) {
         unsigned item = 0;
@@ -529,11 +555,14 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
         gc.learned += __popcll(__ballot(has && gp.used));
         gc.restarts += __popcll(__ballot(has && f.restarted));
         any_noconv = any_noconv || __ballot(has && !f.converged) != 0;
+        if (has) rmax = fmaxf(rmax, (float)f.resid);
     }
     it_sum = wave_sum(it_sum);
     it_max = wave_max(it_max);
+    const unsigned rbits = wave_max(__float_as_uint(rmax));
     if (lane == 0) {
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
+        slot_max_resid(slots, blockIdx.x, rbits);
         slot_add_guess(slots, blockIdx.x, gc);
         if (any_noconv) record_error(cnt, ST_NOCONV, step);
     }
@@ -874,7 +903,8 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     if (opts) h->opts = *opts;
     if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = kep::DEFAULT_TOL;
     if (h->opts.max_iter <= 0) h->opts.max_iter = kep::DEFAULT_MAX_ITER;
-    if (h->opts.max_iter > SAKURA_MAX_ITER ||
+    if (h->opts.max_iter > SAKURA_MAX_ITER || h->opts.tile_override < 0 ||
+        h->opts.tile_override > sk::TILE ||
         (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED)) {
         delete h;
         return SAKURA_EINVAL;
@@ -926,20 +956,33 @@ void sakura_destroy(sakura_t *h)
 
 const char *sakura_last_error(const sakura_t *h) { return h ? h->err.c_str() : "null handle"; }
 
-int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, double *v,
-                         double dt, int64_t nsteps, double G, int scheme, void *stream,
-                         sakura_stats *stats)
+} // extern "C"
+
+namespace {
+
+// Device buffers of one evolve call: the state, the tile partial sums and the
+// counters.  `fixed` marks buffers the caller provides (the allocation-free
+// entry point); otherwise the handle's own buffers are grown as needed.
+struct EvolveBuffers {
+    double *state, *part;
+    sk::DevCounters *cnt;
+    sk::SlotStats *slots;
+    bool fixed;
+};
+
+int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
+               int64_t nsteps, double G, int scheme, void *stream, sakura_stats *stats,
+               EvolveBuffers buf)
 {
-    if (!h) return SAKURA_EINVAL;
-    h->err.clear();
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->failed_step = -1;
     }
-    if (n < 1 || !m || !r || !v) return sk::fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
-    if (n > ((int64_t)1 << 21)) return sk::fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
-    if (!std::isfinite(dt) || !std::isfinite(G) || G < 0.0)
-        return sk::fail(h, SAKURA_EINVAL, "dt and G must be finite and G >= 0");
+    if (n < 2 || !m || !r || !v) return sk::fail(h, SAKURA_EINVAL, "n < 2 or null pointer");
+    if (!std::isfinite(dt) || !std::isfinite(G) || !(G > 0.0))
+        return sk::fail(h, SAKURA_EINVAL, "dt and G must be finite and G > 0");
+    int rc;
+    if (!buf.fixed && (rc = sk::check_capacity(h, n))) return rc;
     if (nsteps < 0) return sk::fail(h, SAKURA_EINVAL, "nsteps < 0");
     Stage stages[3];
     int nstage = 0;
@@ -952,10 +995,15 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((n + sk::TILE - 1) / sk::TILE);
     const int np = nb * sk::TILE;
-    int rc;
-    if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
-    if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE))) return rc;
-    const bool timing = stats != nullptr;
+    if (!buf.fixed) {
+        if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
+        if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE)))
+            return rc;
+        buf.state = h->state;
+        buf.part = h->part;
+    }
+    // the allocation-free path creates no events: it reports no timings
+    const bool timing = stats != nullptr && !buf.fixed;
     const int64_t nlaunch = nsteps * nstage;
     // pair launches are timed with a ring of event pairs: a pair is read back
     // (waiting for the launch it bracketed) before it is recorded again, so a
@@ -979,6 +1027,10 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
                             "(no learned starter, no harvest)");
         mode = 5;
     }
+    if (buf.fixed && (mode == 2 || mode == 3))
+        return sk::fail(h, SAKURA_EINVAL,
+                        "the allocation-free entry point runs the plain starter only "
+                        "(no learned starter, no harvest)");
     if (mode == 2) { // lists of deferred pairs
         if ((rc = sk::grow(h, &h->defer_pairs, &h->cap_defer, (int64_t)ntiles * kep::DEFER_CAP)))
             return rc;
@@ -989,8 +1041,8 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
     }
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
-    sk::k_clear<<<1, sk::NSLOT, 0, st>>>(h->cnt, h->slots);
-    k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, first, h->state, h->cnt);
+    sk::k_clear<<<1, sk::NSLOT, 0, st>>>(buf.cnt, buf.slots);
+    k_import<<<(np + 255) / 256, 256, 0, st>>>((int)n, np, m, r, v, first, buf.state, buf.cnt);
     for (int64_t s = 0; s < nsteps; ++s) {
         for (int k = 0; k < nstage; ++k) {
             const Stage &g = stages[k];
@@ -999,17 +1051,17 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
             if (timing && e >= ring && (rc = read_pair_timing(h, slot, &pair_ms))) return rc;
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * slot], st));
             launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, g.t, g.cb,
-                         g.ca, G, e2, e4, h->state, h->part, h->cnt, h->slots, kp, s, net);
+                         g.ca, G, e2, e4, buf.state, buf.part, buf.cnt, buf.slots, kp, s, net);
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * slot], st));
-            k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, h->state,
-                                                 h->part, h->cnt, s);
+            k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, buf.state,
+                                                 buf.part, buf.cnt, s);
         }
     }
-    k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, h->state, r, v, h->cnt);
-    sk::k_fold_stats<<<1, sk::NSLOT, 0, st>>>(h->slots, h->cnt);
+    k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, buf.state, r, v, buf.cnt);
+    sk::k_fold_stats<<<1, sk::NSLOT, 0, st>>>(buf.slots, buf.cnt);
     SAKURA_HIP(h, hipGetLastError());
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[1], st));
-    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, h->cnt, sizeof(sk::DevCounters), hipMemcpyDeviceToHost, st));
+    SAKURA_HIP(h, hipMemcpyAsync(h->host_cnt, buf.cnt, sizeof(sk::DevCounters), hipMemcpyDeviceToHost, st));
     SAKURA_HIP(h, hipStreamSynchronize(st));
 
     const sk::DevCounters &c = *h->host_cnt;
@@ -1022,17 +1074,33 @@ int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, dou
         for (int k = 0; k < 32; ++k) stats->hist[k] = c.hist[k];
         stats->pair_launches = nlaunch;
         stats->failed_step = c.status ? c.failed_step : -1;
-        for (int64_t k = 0; k < ring; ++k)
-            if ((rc = read_pair_timing(h, (size_t)k, &pair_ms))) return rc;
-        stats->pair_kernel_ms = pair_ms;
-        float ms = 0.0f;
-        SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
-        stats->call_ms = ms;
+        if (timing) {
+            for (int64_t k = 0; k < ring; ++k)
+                if ((rc = read_pair_timing(h, (size_t)k, &pair_ms))) return rc;
+            stats->pair_kernel_ms = pair_ms;
+            float ms = 0.0f;
+            SAKURA_HIP(h, hipEventElapsedTime(&ms, h->events[0], h->events[1]));
+            stats->call_ms = ms;
+        }
     }
     const int code = sk::status_code(c.status);
     if (code) return sk::fail(h, code, std::string(sk::status_text(code)) + " at step " +
                                        std::to_string(c.failed_step));
     return SAKURA_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int sakura_evolve_scheme(sakura_t *h, int64_t n, const double *m, double *r, double *v,
+                         double dt, int64_t nsteps, double G, int scheme, void *stream,
+                         sakura_stats *stats)
+{
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    return evolve_run(h, n, m, r, v, dt, nsteps, G, scheme, stream, stats,
+                      EvolveBuffers{nullptr, nullptr, h->cnt, h->slots, false});
 }
 
 int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v, double dt,
@@ -1062,9 +1130,9 @@ int sakura_energy(sakura_t *h, int64_t n, const double *m, const double *r, cons
 {
     if (!h) return SAKURA_EINVAL;
     h->err.clear();
-    if (n < 1 || !m || !r || !v || !out) return sk::fail(h, SAKURA_EINVAL, "n < 1 or null pointer");
+    if (n < 2 || !m || !r || !v || !out) return sk::fail(h, SAKURA_EINVAL, "n < 2 or null pointer");
     if (n > ((int64_t)1 << 21)) return sk::fail(h, SAKURA_EINVAL, "n > 2^21 exceeds the tile grid");
-    if (!std::isfinite(G)) return sk::fail(h, SAKURA_EINVAL, "G must be finite");
+    if (!std::isfinite(G) || !(G > 0.0)) return sk::fail(h, SAKURA_EINVAL, "G must be finite and > 0");
     SAKURA_HIP(h, hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((n + sk::TILE - 1) / sk::TILE);

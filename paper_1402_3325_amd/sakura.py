@@ -30,7 +30,8 @@ class SakuraError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("guess", ctypes.c_int), ("kepler_rtol", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("histogram", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("histogram", ctypes.c_int),
+                ("tile_override", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -40,7 +41,8 @@ class Stats(ctypes.Structure):
                 ("call_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64),
                 ("failed_step", ctypes.c_int64), ("guess_domain_pairs", ctypes.c_uint64),
                 ("guess_domain_iters", ctypes.c_uint64), ("guess_learned", ctypes.c_uint64),
-                ("guess_restarts", ctypes.c_uint64), ("pair_kicks", ctypes.c_uint64)]
+                ("guess_restarts", ctypes.c_uint64), ("pair_kicks", ctypes.c_uint64),
+                ("max_rel_residual", ctypes.c_double)]
 
     def to_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "hist"}
@@ -133,7 +135,7 @@ def load_library():
     L.sakura_last_error.argtypes = [P]
     L.sakura_last_error.restype = ctypes.c_char_p
     D4 = ctypes.POINTER(ctypes.c_double)
-    L.sakura_set_guess_model.argtypes = [P, ctypes.POINTER(GuessModel)]
+    L.sakura_set_guess_model.argtypes = [P, P, ctypes.c_size_t]
     L.sakura_set_guess.argtypes = [P, ctypes.c_int]
     L.sakura_harvest_begin.argtypes = [P, P, ctypes.c_int64, D4]
     L.sakura_harvest_end.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
@@ -178,11 +180,11 @@ class Sakura:
     """A library handle bound to one GPU."""
 
     def __init__(self, device: int = 0, guess: int = GUESS_ANALYTIC, kepler_rtol: float = 0.0,
-                 max_iter: int = 0, histogram: bool = False):
+                 max_iter: int = 0, histogram: bool = False, tile_override: int = 0):
         self._lib = lib()
         self.device = device
         h = ctypes.c_void_p()
-        o = Opts(guess, kepler_rtol, max_iter, int(bool(histogram)))
+        o = Opts(guess, kepler_rtol, max_iter, int(bool(histogram)), int(tile_override))
         rc = self._lib.sakura_create(ctypes.byref(h), device, ctypes.byref(o))
         if rc != OK:
             raise SakuraError(rc, "sakura_create failed")
@@ -322,11 +324,13 @@ class Sakura:
     def set_guess_model(self, model):
         """Load a GuessModel (or a dict from GuessModel.to_dict); None unloads."""
         if model is None:
-            self._ok(self._lib.sakura_set_guess_model(self._h, None))
+            self._ok(self._lib.sakura_set_guess_model(self._h, None, 0))
             return
         if isinstance(model, dict):
             model = GuessModel.from_dict(model)
-        self._ok(self._lib.sakura_set_guess_model(self._h, ctypes.byref(model)))
+        self._ok(self._lib.sakura_set_guess_model(self._h, ctypes.cast(ctypes.byref(model),
+                                                                       ctypes.c_void_p),
+                                                  ctypes.sizeof(model)))
 
     def set_guess(self, guess: int):
         self._ok(self._lib.sakura_set_guess(self._h, int(guess)))

@@ -80,6 +80,59 @@ def test_batch_matches_oracle_every_step(torch, lib, oracle, policy):
     lib.batch_set_policy(0, 8, True)
 
 
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_in_kernel_steps_equal_single_steps(torch, lib, policy):
+    """One launch of k steps (the state carried in registers, eq. 27a redone in
+    place) against k launches of one step each: bitwise equal, for every
+    packing policy and for items of one, two and four wavefronts (SIZES spans
+    1..64 particles)."""
+    lib.batch_set_policy(policy, 8, True)
+    try:
+        off, m, r, v, tau = small_ensemble(SIZES, seed=31)
+        mt, rk, vk, dtt = _dev(torch, m, r, v, tau)
+        lib.batch_evolve(off, mt, rk, vk, dtt, 6)
+        r1, v1 = _dev(torch, r, v)
+        for _ in range(6):
+            lib.batch_evolve(off, mt, r1, v1, dtt, 1)
+        assert torch.equal(rk, r1) and torch.equal(vk, v1)
+    finally:
+        lib.batch_set_policy(0, 8, True)
+
+
+def test_in_kernel_steps_match_oracle(torch, lib, oracle):
+    """One launch of 8 steps on planetary systems (regular orbits, no chaotic
+    growth over 8 steps) against 8 oracle steps per system, at 1e-12."""
+    off, m, r, v, tau = small_ensemble([16, 64, 33, 9, 3, 40, 24, 2], seed=41)
+    mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+    lib.batch_evolve(off, mt, rt, vt, dtt, 8)
+    rg, vg = rt.cpu().numpy(), vt.cpu().numpy()
+    for s in range(len(off) - 1):
+        a, b = off[s], off[s + 1]
+        ro, vo = oracle.evolve(m[a:b], r[a:b], v[a:b], tau[s], 8)
+        er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
+        assert er <= TOL and ev <= TOL, (s, b - a, er, ev)
+
+
+def test_tile_override_packs_every_system_alike(torch, oracle):
+    """opts.tile_override = 64 gives every system a wavefront of its own and
+    = 8 pads small systems to 8 lanes; both match the oracle per step."""
+    from paper_1402_3325_amd.sakura import Sakura
+    off, m, r, v, tau = small_ensemble(SIZES, seed=51)
+    for ov in (64, 8):
+        h = Sakura(0, tile_override=ov)
+        try:
+            mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+            h.batch_evolve(off, mt, rt, vt, dtt, 1)
+        finally:
+            h.close()
+        rg, vg = rt.cpu().numpy(), vt.cpu().numpy()
+        for s in range(len(SIZES)):
+            a, b = off[s], off[s + 1]
+            ro, vo = oracle.step(m[a:b], r[a:b], v[a:b], tau[s])
+            er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
+            assert er <= TOL and ev <= TOL, (ov, s, er, ev)
+
+
 def test_batch_equals_single_system_path(torch, lib):
     off, m, r, v, tau = small_ensemble([64, 40, 9, 2], seed=9)
     mt, rt, vt, dtt = _dev(torch, m, r, v, tau)

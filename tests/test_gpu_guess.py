@@ -196,6 +196,34 @@ def test_fused_starter_matches_bf16_emulation(torch, lib, oracle):
     assert np.all(info & 8)
 
 
+def test_fused_starter_matches_oracle_network(torch, lib, oracle):
+    """The fused bf16 MFMA inference against the oracle's fp64 network
+    (sref_mlp_forward, no quantisation) on the oracle's own inputs: the
+    network outputs agree normwise to 2e-2, the precision a bf16 network can
+    hold (8 significant bits in weights, inputs and layer-1 activations)."""
+    from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
+    mu, X, W, T = kepler_problems(3000, 23)
+    F, Y, D = oracle_samples(oracle, mu, X, W, T)
+    model = make_model(np.random.default_rng(8), F, D)
+    lib.set_guess_model(model)
+    try:
+        lib.set_guess(GUESS_LEARNED)
+        s0, _, info = run_eval(torch, lib, mu, X, W, T)
+    finally:
+        lib.set_guess(GUESS_ANALYTIC)
+        lib.set_guess_model(None)
+    k = np.where((info & 2).astype(bool))[0]
+    assert len(k) > 300
+    xs = (F[k] - np.array(model["in_shift"])) * np.array(model["in_scale"])
+    o_ref = oracle.mlp_forward(np.asarray(model["params"], dtype=np.float64), xs)
+    r0 = np.linalg.norm(X[k], axis=1)
+    y_gpu = np.log(s0[k] * r0 / reduced_time(mu, X, W, T)[k])
+    o_gpu = (y_gpu - model["out_shift"]) / model["out_scale"]
+    rel = np.linalg.norm(o_gpu - o_ref) / np.linalg.norm(o_ref)
+    print(f"fused bf16 network vs fp64 oracle network: normwise {rel:.2e} over {len(k)} pairs")
+    assert rel <= 2e-2
+
+
 def test_root_search_plain_and_learned_agree(torch, lib, oracle):
     from paper_1402_3325_amd.sakura import GUESS_ANALYTIC, GUESS_LEARNED
     mu, X, W, T = kepler_problems(3000, 22)

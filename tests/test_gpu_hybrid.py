@@ -80,7 +80,7 @@ def test_hybrid_cluster_16384_sampled(torch, lib, oracle):
     rng = np.random.default_rng(17)
     rin, vin = r, v
     for _ in range(3):
-        rows = _cluster_rows(m, rng)
+        rows = _cluster_rows(m, rin, rng)
         rg, vg, st = gpu_hybrid(torch, lib, m, rin, vin, tau, 0.01)
         ro, vo = oracle.step_rows_hybrid(m, rin, vin, tau, 0.01, rows)
         er, ev = step_error(rg[rows], vg[rows], ro, vo, rin[rows], vin[rows])

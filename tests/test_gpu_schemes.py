@@ -40,10 +40,10 @@ def lib(torch):
     h.close()
 
 
-def conditioned_tol(oracle, m, r, v, dt, sid, eps=1e-14, trials=3):
+def conditioned_tol(oracle, m, r, v, dt, sid, eps=2.0 ** -52, trials=3):
     """(tolerance, oracle result): max(TOL, 10 S), S the largest step error
     between the oracle's step from (r, v) and from (r, v) perturbed by a
-    relative eps."""
+    relative eps (one unit in the last place)."""
     ro, vo = oracle.evolve_scheme(m, r, v, dt, 1, sid)
     rng = np.random.default_rng(0)
     sens = 0.0
