@@ -124,6 +124,25 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                   double dt, int64_t nsteps, double G, void *stream,
                   sakura_stats *stats);
 
+/* Allocation-free variant of sakura_evolve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It runs the same kernels on a static device array of
+ * the library (12.4 MB: state, partial sums and counters for up to
+ * SAKURA_NOALLOC_MAX_N particles) instead of handle-owned buffers, and calls
+ * no allocating routine.  Each device the library runs on holds one copy of
+ * that array until the process ends; every call on a device shares it and it
+ * keeps the last call's contents (the kernels clear what must start at zero),
+ * so calls that overlap on one device -- from several threads, handles or
+ * streams -- race, and the caller must serialise them.  Runs the merged step
+ * (eq. 25) with the plain starter, or the close-pair hybrid when it is on;
+ * stats get the counters but no timings.  Arguments, ownership and errors as
+ * sakura_evolve; EINVAL also for n > SAKURA_NOALLOC_MAX_N, the learned
+ * starter and a running harvest. */
+#define SAKURA_NOALLOC_MAX_N 4096
+int sakura_evolve_noalloc(sakura_t *h, int64_t n, const double *m, double *r, double *v,
+                          double dt, int64_t nsteps, double G, void *stream,
+                          sakura_stats *stats);
+
 /* Compositions of the step (Sec. 2.2).  A W stage applies eqs. (27b, 27c)
  * with a pair map made of a back-drift cb of the relative position, the Kepler
  * flow over t and a back-drift ca (t = cb + ca); stages are separated by free

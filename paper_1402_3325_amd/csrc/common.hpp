@@ -174,6 +174,10 @@ struct sakura {
     bool harvesting = false;
     kep::GuessNet harvest{};      // domain and row buffer of the harvest
     unsigned long long *row_count = nullptr;
+    // device address of the allocation-free entry point's static scratch on
+    // this handle's device (null, with the reason, if it could not be resolved)
+    void *noalloc_scratch = nullptr;
+    std::string noalloc_err;
     // network training scratch
     float *mlp_buf = nullptr;
     int64_t cap_mlp = 0;

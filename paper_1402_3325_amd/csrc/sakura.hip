@@ -13,6 +13,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 __global__ void sk::k_clear(DevCounters *c, SlotStats *slots)
 {
@@ -889,6 +890,55 @@ int need_events(sakura_t *h, size_t count)
 
 } // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of sakura_evolve_noalloc: state, tile partial sums, counter
+// slots and counters for up to NOALLOC_MAX_N particles (12.4 MB), one copy on
+// every device the library runs on, held until the process ends.  Host code
+// never hands `scratch` itself to a kernel (in host code the name is only a
+// stand-in): its device address comes from hipGetSymbolAddress, once per
+// device, with that device current (sakura_create), and only that address is
+// used.
+namespace {
+constexpr int NOALLOC_MAX_N = SAKURA_NOALLOC_MAX_N;
+constexpr size_t NOALLOC_NB = NOALLOC_MAX_N / sk::TILE;
+constexpr size_t NOALLOC_STATE = 10 * (size_t)NOALLOC_MAX_N;            // doubles
+constexpr size_t NOALLOC_PART = NOALLOC_NB * NOALLOC_NB * 6 * sk::TILE; // doubles
+constexpr size_t NOALLOC_SLOTS = sk::NSLOT * sizeof(sk::SlotStats) / sizeof(double);
+constexpr size_t NOALLOC_CNT = (sizeof(sk::DevCounters) + 255) / 256 * 256 / sizeof(double);
+constexpr size_t NOALLOC_DOUBLES = NOALLOC_STATE + NOALLOC_PART + NOALLOC_SLOTS + NOALLOC_CNT;
+static_assert(NOALLOC_MAX_N % sk::TILE == 0, "whole tiles");
+static_assert((NOALLOC_STATE * sizeof(double)) % 256 == 0 &&
+                  (NOALLOC_PART * sizeof(double)) % 256 == 0 &&
+                  (NOALLOC_SLOTS * sizeof(double)) % 256 == 0,
+              "256-byte aligned sub-buffers");
+} // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[NOALLOC_MAX_DEVICES] = {}; // device address of `scratch`, per device
+
+// The device address of `scratch` on `device` (current), resolved once per
+// device; hipSuccess or the error of hipGetSymbolAddress.
+hipError_t scratch_address(int device, void **addr)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *addr = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *addr = g_scratch_addr[device];
+    return hipSuccess;
+}
+} // namespace
+
 extern "C" {
 
 int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
@@ -917,6 +967,11 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
         sakura_destroy(h);
         return SAKURA_EHIP;
     }
+    // the allocation-free entry point's scratch on this device (a failure is
+    // reported by that entry point; the others do not need it)
+    const hipError_t se = scratch_address(device, &h->noalloc_scratch);
+    if (se != hipSuccess)
+        h->noalloc_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(se);
     *out = h;
     return SAKURA_OK;
 }
@@ -1107,6 +1162,34 @@ int sakura_evolve(sakura_t *h, int64_t n, const double *m, double *r, double *v,
                   int64_t nsteps, double G, void *stream, sakura_stats *stats)
 {
     return sakura_evolve_scheme(h, n, m, r, v, dt, nsteps, G, SAKURA_SCHEME_PSI, stream, stats);
+}
+
+int sakura_evolve_noalloc(sakura_t *h, int64_t n, const double *m, double *r, double *v,
+                          double dt, int64_t nsteps, double G, void *stream,
+                          sakura_stats *stats)
+{
+    if (!h) return SAKURA_EINVAL;
+    h->err.clear();
+    if (n > NOALLOC_MAX_N) {
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->failed_step = -1;
+        }
+        return sk::fail(h, SAKURA_EINVAL,
+                        "n = " + std::to_string(n) + " exceeds the " +
+                            std::to_string(NOALLOC_MAX_N) +
+                            " particles of the allocation-free entry point's static scratch");
+    }
+    if (!h->noalloc_scratch)
+        return sk::fail(h, SAKURA_EHIP, "no device address for the static scratch: " +
+                                            h->noalloc_err);
+    double *base = static_cast<double *>(h->noalloc_scratch);
+    EvolveBuffers buf{base, base + NOALLOC_STATE,
+                      reinterpret_cast<sk::DevCounters *>(base + NOALLOC_STATE + NOALLOC_PART +
+                                                          NOALLOC_SLOTS),
+                      reinterpret_cast<sk::SlotStats *>(base + NOALLOC_STATE + NOALLOC_PART),
+                      true};
+    return evolve_run(h, n, m, r, v, dt, nsteps, G, SAKURA_SCHEME_PSI, stream, stats, buf);
 }
 
 int sakura_set_hybrid(sakura_t *h, double eta)

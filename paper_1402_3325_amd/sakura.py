@@ -20,6 +20,7 @@ ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "ENONFINITE", -3: "ECOLLIDE", -4: "ENO
                -5: "EHIP", -6: "ENOMEM", -7: "ENOMODEL"}
 GUESS_ANALYTIC, GUESS_LEARNED = 0, 1
 SCHEME_PSI, SCHEME_UNMERGED, SCHEME_TRIPLE_JUMP = 0, 1, 2
+NOALLOC_MAX_N = 4096
 
 
 class SakuraError(RuntimeError):
@@ -111,6 +112,10 @@ def load_library():
     L.sakura_evolve.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_int64,
                                 ctypes.c_double, P, ctypes.POINTER(Stats)]
     L.sakura_evolve.restype = ctypes.c_int
+    L.sakura_evolve_noalloc.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
+                                        ctypes.c_int64, ctypes.c_double, P,
+                                        ctypes.POINTER(Stats)]
+    L.sakura_evolve_noalloc.restype = ctypes.c_int
     L.sakura_evolve_scheme.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_double,
                                        ctypes.c_int64, ctypes.c_double, ctypes.c_int, P,
                                        ctypes.POINTER(Stats)]
@@ -222,6 +227,21 @@ class Sakura:
                                      ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(v.data_ptr()),
                                      float(dt), int(nsteps), float(G), self._stream(m),
                                      ctypes.byref(st) if stats else None)
+        if rc != OK:
+            self._raise(rc)
+        return st.to_dict() if stats else None
+
+    def evolve_noalloc(self, m, r, v, dt: float, nsteps: int, G: float = 1.0,
+                       stats: bool = False):
+        """sakura_evolve on the library's static scratch (no device allocation;
+        n <= NOALLOC_MAX_N; calls on one device must not overlap)."""
+        n = self._state(m, r, v)
+        st = Stats()
+        rc = self._lib.sakura_evolve_noalloc(self._h, n, ctypes.c_void_p(m.data_ptr()),
+                                             ctypes.c_void_p(r.data_ptr()),
+                                             ctypes.c_void_p(v.data_ptr()), float(dt),
+                                             int(nsteps), float(G), self._stream(m),
+                                             ctypes.byref(st) if stats else None)
         if rc != OK:
             self._raise(rc)
         return st.to_dict() if stats else None
