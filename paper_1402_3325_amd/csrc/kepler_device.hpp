@@ -104,6 +104,28 @@ SAKURA_HD inline double sqrt_step(double x) // about 2^-46, x >= 0
     return x * y;
 }
 
+// z + c and a b + c with the constant c read from a scalar register pair by
+// the vector operation itself; left to the compiler, such a constant is moved
+// into two vector registers first (as the accumulator of a v_fmac), which
+// costs two vector instructions on the unit that bounds the pair kernels.
+#ifndef SAKURA_NO_SCALAR_ASM
+SAKURA_HD inline double add_sc(double z, double c)
+{
+    double r;
+    asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(z), "s"(c));
+    return r;
+}
+SAKURA_HD inline double fma_sc(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+#else
+inline double add_sc(double z, double c) { return z + c; }
+inline double fma_sc(double a, double b, double c) { return fma(a, b, c); }
+#endif
+
 // The same functions for |z| <= 2^-10 only: four terms each leave a truncation
 // below 1e-18 relative.
 SAKURA_HD inline void stumpff23_small(double z, double &c2, double &c3)
@@ -156,8 +178,8 @@ SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double z
         // 1/2 - z/24 + z^2/720 and 1/6 - z/120 + z^2/5040, written with one
         // non-trivial constant per operation (a VALU operation reads at most
         // one scalar), which saves the moves of constants into vector registers
-        c2 = fma((1.0 / 720.0) * z, z - 30.0, 0.5);
-        c3 = fma((1.0 / 5040.0) * z, z - 42.0, 1.0 / 6.0);
+        c2 = fma((1.0 / 720.0) * z, add_sc(z, -30.0), 0.5);
+        c3 = fma_sc((1.0 / 5040.0) * z, add_sc(z, -42.0), 1.0 / 6.0);
     } else if (TIER == 1) {
         stumpff23_small(z, c2, c3);
     } else {
@@ -239,18 +261,41 @@ SAKURA_HD inline void taylor_shift3(KepIter &st, const KepEval &e, double d, dou
 // bound through 2 |corr1| and 6 |A3 u^2| <= 6 (c + 2 c^2)), so
 // C s^2 <= 6.2 c + 67 c^2 <= 0.0124, and a step with |ds| <= 2^-16 |s - ds|
 // leaves an error below 2^-48 C s^2 |s - ds| <= tol |s - ds| / 4.
+//
+// With NEWTON as well (EASY and tol >= 2^-50) the step is Newton's,
+// ds = F / r, when every lane of the wavefront has |ds| <= 2^-23 |s - ds|:
+// its error is t2 ds^2 / (2 r) to leading order, and |t2 s / r| <= 8.2 c
+// bounds it by 4.1 c (ds/s)^2 |s| <= 2^-52.96 |s|, below tol |s| / 4 (the
+// starter's own error, about the square of its corrections times u, is below
+// 2^-23 for 99.9 % of a star cluster's easy wavefronts).  Otherwise the
+// Halley step is taken as before.  The two agree to a relative F F'' / 2 r^2
+// of the step, below the rounding of the root here.
 template <int TIER>
 SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double zeta, double r0,
-                                  double t, double tol, bool easy)
+                                  double t, double tol, bool easy, bool newton)
 {
     const double s = st.s;
     const KepEval e = kepler_eval<TIER>(s, beta, eta, zeta, r0, t);
-    const double ds = laguerre_step<TIER == 2>(e);
+    double ds;
+    bool nt = false;
+    if (TIER == 2 && newton) {
+        const double dn = e.F * rcp_step(e.r);
+        if (SAKURA_WAVE_ALL(fabs(dn) <= 0x1p-23 * fabs(s - dn))) {
+            ds = dn;
+            nt = true;
+        } else {
+            ds = laguerre_step<true>(e);
+        }
+    } else {
+        ds = laguerre_step<TIER == 2>(e);
+    }
     const double ads = fabs(ds);
     const double sn = s - ds;
     const double asn = fabs(sn);
     bool done;
-    if (TIER == 2 && easy)
+    if (TIER == 2 && nt)
+        done = true;
+    else if (TIER == 2 && easy)
         done = ads <= tol * fabs(s) || e.F == 0.0 || ads <= 0x1p-16 * asn;
     else
         done = ads <= tol * fabs(s) || e.F == 0.0 ||
@@ -442,16 +487,16 @@ struct NoGuess {
 // general tier.
 SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double zeta, double r0,
                                    double t, double u, double s_half, const KeplerParams &kp,
-                                   bool easy, int &it)
+                                   bool easy, int &it, bool newton = false)
 {
     const double z0 = fabs(beta * st.s * st.s);
     int res;
     if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
-        res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol, easy);
+        res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol, easy, newton);
     else if (SAKURA_WAVE_ALL(z0 <= 0x1p-10))
-        res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol, false);
+        res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol, false, false);
     else
-        res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol, false);
+        res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol, false, false);
     it = 1;
     if (res == 0) {
         initial_bracket(t, u, beta, eta, s_half, st.lo, st.hi);
@@ -518,7 +563,8 @@ SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau,
     const bool easy = kp.tol >= 0x1p-52 && SAKURA_WAVE_ALL(csum <= 0x1p-9 && !replaced);
     KepIter st{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
     int it = 0;
-    int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, easy, it);
+    int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, easy, it,
+                            easy && kp.tol >= 0x1p-50);
     bool restarted = false;
     if (Guess::active && res == 0 && replaced) {
         restarted = true;

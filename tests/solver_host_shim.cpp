@@ -15,6 +15,7 @@ using std::rint;
 using std::sqrt;
 #define SAKURA_HD
 #define SAKURA_WAVE_ALL(p) (p)
+#define SAKURA_NO_SCALAR_ASM
 #define __builtin_amdgcn_rcp(x) ((1.0 / (x)) * (1.0 + 6e-8))
 #define __builtin_amdgcn_rsq(x) ((1.0 / std::sqrt(x)) * (1.0 - 6e-8))
 #include "../paper_1402_3325_amd/csrc/kepler_device.hpp"
