@@ -67,6 +67,8 @@ def lib():
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                             _I64, _D, _D]
         L.sref_energy.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double, _D]
+        L.sref_row_terms.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int64, _D, _D]
         L.sref_num_threads.restype = ctypes.c_int
         L.sref_set_num_threads.argtypes = [ctypes.c_int]
         L.sref_set_num_threads.restype = None
@@ -240,6 +242,22 @@ def step_rows(m, r, v, tau, rows, G=1.0):
     if rc:
         raise OracleError(rc, "sref_step_rows")
     return ro, vo
+
+
+def row_terms(m, r, v, tau, i, G=1.0):
+    """The weighted increments w_ij dr_ij, w_ij dv_ij ([n, 3] each) that row i
+    of one step sums."""
+    m = _f64(m)
+    n = m.shape[0]
+    r = _f64(r, (n, 3))
+    v = _f64(v, (n, 3))
+    dr = np.empty((n, 3))
+    dv = np.empty((n, 3))
+    rc = lib().sref_row_terms(n, _p(m), _p(r), _p(v), float(tau), float(G), int(i), _p(dr),
+                              _p(dv))
+    if rc:
+        raise OracleError(rc, "sref_row_terms")
+    return dr, dv
 
 
 def energy(m, r, v, G=1.0):

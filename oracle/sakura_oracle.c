@@ -424,6 +424,38 @@ static int step_row(int64_t n, const double *m, const double *rh,
 }
 
 static int check_args(int64_t n, const double *m, const double *r,
+                      const double *v, double tau, double G);
+static double *half_drift(int64_t n, const double *r, const double *v, double tau);
+
+/* The weighted increments w_ij (dr_ij, dv_ij) that row i of eqs. (27b, c) sums,
+ * one per partner j (zero for j = i and for massless pairs), in double. */
+int sref_row_terms(int64_t n, const double *m, const double *r, const double *v, double tau,
+                   double G, int64_t i, double *dr_terms, double *dv_terms)
+{
+    int rc = check_args(n, m, r, v, tau, G);
+    if (rc) return rc;
+    if (i < 0 || i >= n || !dr_terms || !dv_terms) return SREF_EINVAL;
+    double *rh = half_drift(n, r, v, tau);
+    if (!rh) return SREF_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int c = 0; c < 3; ++c) dr_terms[3 * j + c] = dv_terms[3 * j + c] = 0.0;
+        double mij = m[i] + m[j];
+        if (j == i || mij == 0.0) continue;
+        double w = m[j] / mij;
+        double dr[3], dv[3];
+        rc = sref_pair_increment(tau, G, m[i], m[j], rh + 3 * i, v + 3 * i, rh + 3 * j,
+                                 v + 3 * j, SREF_SOLVER_KEPLER, dr, dv);
+        if (rc) break;
+        for (int c = 0; c < 3; ++c) {
+            dr_terms[3 * j + c] = w * dr[c];
+            dv_terms[3 * j + c] = w * dv[c];
+        }
+    }
+    free(rh);
+    return rc;
+}
+
+static int check_args(int64_t n, const double *m, const double *r,
                       const double *v, double tau, double G)
 {
     if (n < 1 || !m || !r || !v) return SREF_EINVAL;

@@ -61,6 +61,11 @@ int sref_step_rows(int64_t n, const double *m, const double *r, const double *v,
                    double tau, double G, int64_t nrows, const int64_t *rows,
                    double *r_out, double *v_out);
 
+/* The terms row i of eqs. (27b, 27c) sums: w_ij dr_ij and w_ij dv_ij for every
+ * partner j ([n][3] each, zero for j = i and massless pairs). */
+int sref_row_terms(int64_t n, const double *m, const double *r, const double *v, double tau,
+                   double G, int64_t i, double *dr_terms, double *dv_terms);
+
 /* nsteps calls of sref_step. */
 int sref_evolve(int64_t n, const double *m, double *r, double *v, double tau,
                 int64_t nsteps, double G, int solver);
