@@ -210,13 +210,27 @@ int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_g
 /* Lanes used by systems of exactly n particles (n <= lanes <= 64). */
 int sakura_batch_set_group(sakura_t *h, int n, int lanes);
 
-/* Time every packing policy and grid size on this ensemble for probe_steps
- * steps (on scratch copies; r and v are not modified), keep the fastest on the
- * handle and report its time in *best_ms (may be NULL).  If a probe fails,
- * its error is returned and the handle keeps the settings it had. */
+/* Tune the packing on this ensemble (scratch copies; r and v are not
+ * modified): the grid size (4, 8 or 16 wavefronts per compute unit), then for
+ * each size bucket the ensemble has systems in (1-8, 9-16, 17-32, 33-64
+ * particles) the lane policy of sakura_batch_set_policy, one coordinate at a
+ * time.  Each probe runs probe_steps steps with the handle's graph use (a new
+ * setting is captured by its first call) and takes the least of two timed
+ * calls after that.  The best settings stay on the handle and are recorded in
+ * its packing table under (gfx architecture, compute units, bucket); the
+ * least probe time goes to *best_ms (may be NULL).  If a probe fails, its
+ * error is returned and the handle keeps the settings it had. */
 int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
                           const double *r, const double *v, const double *dt,
                           int64_t probe_steps, double G, void *stream, double *best_ms);
+
+/* The packing table as a text file (one line per entry: arch, compute units,
+ * bucket 0-3, policy 0-2, wavefronts per compute unit; '#' lines are
+ * comments).  Load merges the file's entries into the handle's table and
+ * applies those of the handle's device; EINVAL for an unreadable or malformed
+ * file (the table is then unchanged). */
+int sakura_batch_table_save(const sakura_t *h, const char *path);
+int sakura_batch_table_load(sakura_t *h, const char *path);
 
 /* ---------------------------------------------------------------------------
  * Learned Kepler starter (an extension of the method; the paper's solver

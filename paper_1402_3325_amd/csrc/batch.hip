@@ -531,6 +531,84 @@ int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_g
     return SAKURA_OK;
 }
 
+} // extern "C"
+
+namespace {
+
+// System-size buckets of the packing table: 1..8, 9..16, 17..32, 33..64
+// particles (items of one wavefront with several systems, of one wavefront, of
+// two and of four wavefronts).
+constexpr int NBUCKET = 4;
+constexpr int BUCKET_LO[NBUCKET] = {1, 9, 17, 33};
+constexpr int BUCKET_HI[NBUCKET] = {8, 16, 32, 64};
+
+void set_bucket_policy(sakura_t *h, int b, int policy)
+{
+    for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n) h->batch_group[n] = policy_group(policy, n);
+}
+
+// The device's identity in the table: its gfx architecture and compute units.
+void device_identity(int device, std::string &arch, int &cus)
+{
+    hipDeviceProp_t prop;
+    arch = "unknown";
+    cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':'); // feature suffixes do not matter here
+        if (colon != std::string::npos) arch.resize(colon);
+        cus = prop.multiProcessorCount;
+    }
+}
+
+// Apply the handle's table entries for this device: per-bucket policy and the
+// grid size (the grid of the last entry that names one).
+void apply_table(sakura_t *h)
+{
+    std::string arch;
+    int cus;
+    device_identity(h->device, arch, cus);
+    for (const auto &e : h->batch_table)
+        if (e.arch == arch && e.cus == cus && e.bucket >= 0 && e.bucket < NBUCKET) {
+            set_bucket_policy(h, e.bucket, e.policy);
+            h->batch_waves_per_cu = e.waves_per_cu;
+        }
+}
+
+// One probe: the ensemble on scratch copies of r and v, probe_steps steps,
+// with the handle's current settings and graph use.  The first call captures
+// (or warms up); the time is the least of the next `reps` calls.
+int probe(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m, const double *r,
+          const double *v, const double *dt, int64_t probe_steps, double G, void *stream,
+          int reps, double *ms)
+{
+    using namespace sk;
+    const int64_t ntot = offsets[nsys];
+    hipStream_t st = (hipStream_t)stream;
+    double best = 1e300;
+    for (int rep = 0; rep <= reps; ++rep) {
+        hipError_t e = hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
+                                      hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->tune_rv + 3 * ntot, v, 3 * ntot * sizeof(double),
+                               hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess)
+            return fail(h, SAKURA_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+        sakura_stats s;
+        const int rc = sakura_batch_evolve(h, nsys, offsets, m, h->tune_rv,
+                                           h->tune_rv + 3 * ntot, dt, probe_steps, G, stream,
+                                           &s);
+        if (rc) return rc;
+        if (rep > 0) best = std::min(best, s.call_ms);
+    }
+    *ms = best;
+    return SAKURA_OK;
+}
+
+} // namespace
+
+extern "C" {
+
 int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m,
                           const double *r, const double *v, const double *dt,
                           int64_t probe_steps, double G, void *stream, double *best_ms)
@@ -540,11 +618,6 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
     const int64_t ntot = offsets[nsys];
     int rc;
     if ((rc = grow(h, &h->tune_rv, &h->cap_tune, 6 * ntot))) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    const int waves[3] = {4, 8, 16};
-    double best = 1e300;
-    int best_policy = 0, best_waves = 8;
-    const int keep_graph = !h->batch_no_graph;
     // a failed probe leaves the handle's batch settings as they were
     int saved_group[TILE + 1];
     std::memcpy(saved_group, h->batch_group, sizeof(saved_group));
@@ -552,37 +625,129 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
     auto restore = [&](int code) {
         std::memcpy(h->batch_group, saved_group, sizeof(saved_group));
         h->batch_waves_per_cu = saved_waves;
-        h->batch_no_graph = !keep_graph;
         return code;
     };
-    for (int policy = 0; policy < 3; ++policy) {
-        for (int wi = 0; wi < 3; ++wi) {
-            sakura_batch_set_policy(h, policy, waves[wi], 0);
-            double t = 0.0;
-            for (int rep = 0; rep < 2; ++rep) { // first run warms up
-                hipError_t e = hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
-                                              hipMemcpyDeviceToDevice, st);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(h->tune_rv + 3 * ntot, v, 3 * ntot * sizeof(double),
-                                       hipMemcpyDeviceToDevice, st);
-                if (e != hipSuccess)
-                    return restore(fail(h, SAKURA_EHIP, std::string("hipMemcpyAsync: ") +
-                                                            hipGetErrorString(e)));
-                sakura_stats s;
-                rc = sakura_batch_evolve(h, nsys, offsets, m, h->tune_rv, h->tune_rv + 3 * ntot,
-                                         dt, probe_steps, G, stream, &s);
-                if (rc) return restore(rc);
-                t = s.call_ms;
-            }
+    // the buckets this ensemble has systems in
+    bool present[NBUCKET] = {false, false, false, false};
+    for (int64_t k = 0; k < nsys; ++k) {
+        const int64_t n = offsets[k + 1] - offsets[k];
+        for (int b = 0; b < NBUCKET; ++b)
+            if (n >= BUCKET_LO[b] && n <= BUCKET_HI[b]) present[b] = true;
+    }
+    // Probes run with the handle's graph setting (a new policy or grid changes
+    // the captured graph, so each probe captures first and times replays),
+    // coordinate by coordinate: the grid size with the current packing, then
+    // each present bucket's packing policy with the others kept.
+    const int reps = 2;
+    double best = 1e300;
+    if ((rc = probe(h, nsys, offsets, m, r, v, dt, probe_steps, G, stream, reps, &best)))
+        return restore(rc);
+    for (const int wpc : {4, 8, 16}) {
+        if (wpc == h->batch_waves_per_cu) continue;
+        const int keep = h->batch_waves_per_cu;
+        h->batch_waves_per_cu = wpc;
+        double t;
+        if ((rc = probe(h, nsys, offsets, m, r, v, dt, probe_steps, G, stream, reps, &t)))
+            return restore(rc);
+        if (t < best) best = t;
+        else h->batch_waves_per_cu = keep;
+    }
+    int chosen[NBUCKET] = {-1, -1, -1, -1};
+    for (int b = 0; b < NBUCKET; ++b) {
+        if (!present[b]) continue;
+        int keep_group[TILE + 1];
+        std::memcpy(keep_group, h->batch_group, sizeof(keep_group));
+        int best_p = -1;
+        for (int p = 0; p < 3; ++p) {
+            set_bucket_policy(h, b, p);
+            double t;
+            if ((rc = probe(h, nsys, offsets, m, r, v, dt, probe_steps, G, stream, reps, &t)))
+                return restore(rc);
             if (t < best) {
                 best = t;
-                best_policy = policy;
-                best_waves = waves[wi];
+                best_p = p;
+                std::memcpy(keep_group, h->batch_group, sizeof(keep_group));
+            }
+        }
+        std::memcpy(h->batch_group, keep_group, sizeof(keep_group));
+        // the policy the bucket holds now (probed or kept)
+        chosen[b] = best_p;
+        if (best_p < 0) {
+            for (int p = 0; p < 3; ++p) {
+                bool same = true;
+                for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n)
+                    same = same && h->batch_group[n] == policy_group(p, n);
+                if (same) {
+                    chosen[b] = p;
+                    break;
+                }
             }
         }
     }
-    sakura_batch_set_policy(h, best_policy, best_waves, keep_graph);
+    // record the choice in the handle's table for this device
+    std::string arch;
+    int cus;
+    device_identity(h->device, arch, cus);
+    for (int b = 0; b < NBUCKET; ++b) {
+        if (chosen[b] < 0) continue;
+        bool found = false;
+        for (auto &e : h->batch_table)
+            if (e.arch == arch && e.cus == cus && e.bucket == b) {
+                e.policy = chosen[b];
+                e.waves_per_cu = h->batch_waves_per_cu;
+                found = true;
+            }
+        if (!found) h->batch_table.push_back({arch, cus, b, chosen[b], h->batch_waves_per_cu});
+    }
     if (best_ms) *best_ms = best;
+    return SAKURA_OK;
+}
+
+int sakura_batch_table_save(const sakura_t *h, const char *path)
+{
+    if (!h || !path) return SAKURA_EINVAL;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return SAKURA_EINVAL;
+    std::fprintf(f, "# sakura batched packing table: arch cus bucket(1-8,9-16,17-32,33-64) "
+                    "policy(0 dense,1 even,2 pow2) waves_per_cu\n");
+    for (const auto &e : h->batch_table)
+        std::fprintf(f, "%s %d %d %d %d\n", e.arch.c_str(), e.cus, e.bucket, e.policy,
+                     e.waves_per_cu);
+    return std::fclose(f) == 0 ? SAKURA_OK : SAKURA_EINVAL;
+}
+
+int sakura_batch_table_load(sakura_t *h, const char *path)
+{
+    if (!h || !path) return SAKURA_EINVAL;
+    h->err.clear();
+    FILE *f = std::fopen(path, "r");
+    if (!f) return sk::fail(h, SAKURA_EINVAL, std::string("cannot open ") + path);
+    std::vector<sakura::BatchTuneEntry> rows;
+    char line[512];
+    int bad = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char arch[128];
+        int cus, b, p, w;
+        if (std::sscanf(line, "%127s %d %d %d %d", arch, &cus, &b, &p, &w) != 5 || b < 0 ||
+            b >= NBUCKET || p < 0 || p > 2 || w < 1 || w > 32) {
+            bad = 1;
+            break;
+        }
+        rows.push_back({arch, cus, b, p, w});
+    }
+    std::fclose(f);
+    if (bad) return sk::fail(h, SAKURA_EINVAL, std::string("malformed table line in ") + path);
+    for (const auto &r : rows) {
+        bool found = false;
+        for (auto &e : h->batch_table)
+            if (e.arch == r.arch && e.cus == r.cus && e.bucket == r.bucket) {
+                e = r;
+                found = true;
+            }
+        if (!found) h->batch_table.push_back(r);
+    }
+    apply_table(h);
     return SAKURA_OK;
 }
 

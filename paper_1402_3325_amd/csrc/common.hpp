@@ -160,6 +160,14 @@ struct sakura {
     int64_t cap_tune = 0;
     int batch_waves_per_cu = 8;
     int batch_no_graph = 0;
+    // packing table: per (gfx arch, compute units, system-size bucket) the
+    // lane policy and grid size that sakura_autotune_batch chose or a table
+    // file supplied
+    struct BatchTuneEntry {
+        std::string arch;
+        int cus, bucket, policy, waves_per_cu;
+    };
+    std::vector<BatchTuneEntry> batch_table;
     // learned starter
     void *net_buf = nullptr;      // packed bf16 fragments and fp32 vectors of the network
     int2 *defer_pairs = nullptr;  // deferred-pair lists of the tile kernel

@@ -137,6 +137,10 @@ def load_library():
                                         P, ctypes.c_int64, ctypes.c_double, P,
                                         ctypes.POINTER(ctypes.c_double)]
     L.sakura_autotune_batch.restype = ctypes.c_int
+    L.sakura_batch_table_save.argtypes = [P, ctypes.c_char_p]
+    L.sakura_batch_table_save.restype = ctypes.c_int
+    L.sakura_batch_table_load.argtypes = [P, ctypes.c_char_p]
+    L.sakura_batch_table_load.restype = ctypes.c_int
     L.sakura_last_error.argtypes = [P]
     L.sakura_last_error.restype = ctypes.c_char_p
     D4 = ctypes.POINTER(ctypes.c_double)
@@ -322,6 +326,15 @@ class Sakura:
         if rc != OK:
             self._raise(rc)
         return best.value
+
+    def batch_table_save(self, path):
+        """Write the handle's packing table (autotuned entries) to a text file."""
+        self._ok(self._lib.sakura_batch_table_save(self._h, str(path).encode()))
+
+    def batch_table_load(self, path):
+        """Merge a packing table file into the handle's and apply this device's
+        entries."""
+        self._ok(self._lib.sakura_batch_table_load(self._h, str(path).encode()))
 
     def energy(self, m, r, v, G: float = 1.0):
         """{E, K, U, P, L, Rcm} of eqs. (1-3), computed on the GPU."""
