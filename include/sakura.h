@@ -214,9 +214,8 @@ int sakura_batch_set_group(sakura_t *h, int n, int lanes);
  * modified): the grid size (4, 8 or 16 wavefronts per compute unit), then for
  * each size bucket the ensemble has systems in (1-8, 9-16, 17-32, 33-64
  * particles) the lane policy of sakura_batch_set_policy, one coordinate at a
- * time.  Each probe runs probe_steps steps with the handle's graph use (a new
- * setting is captured by its first call) and takes the least of two timed
- * calls after that.  The best settings stay on the handle and are recorded in
+ * time.  Each probe runs probe_steps steps with direct launches (no graph)
+ * and takes the least of two timed calls after a warm-up call.  The best settings stay on the handle and are recorded in
  * its packing table under (gfx architecture, compute units, bucket); the
  * least probe time goes to *best_ms (may be NULL).  If a probe fails, its
  * error is returned and the handle keeps the settings it had. */

@@ -576,8 +576,9 @@ void apply_table(sakura_t *h)
 }
 
 // One probe: the ensemble on scratch copies of r and v, probe_steps steps,
-// with the handle's current settings and graph use.  The first call captures
-// (or warms up); the time is the least of the next `reps` calls.
+// with the handle's current packing, its launches made directly (no graph
+// capture per probe).  The first call warms up; the time is the least of the
+// next `reps` calls.
 int probe(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m, const double *r,
           const double *v, const double *dt, int64_t probe_steps, double G, void *stream,
           int reps, double *ms)
@@ -586,6 +587,13 @@ int probe(sakura_t *h, int64_t nsys, const int64_t *offsets, const double *m, co
     const int64_t ntot = offsets[nsys];
     hipStream_t st = (hipStream_t)stream;
     double best = 1e300;
+    const int keep_no_graph = h->batch_no_graph;
+    h->batch_no_graph = 1;
+    struct Restore {
+        sakura_t *h;
+        int v;
+        ~Restore() { h->batch_no_graph = v; }
+    } restore_graph{h, keep_no_graph};
     for (int rep = 0; rep <= reps; ++rep) {
         hipError_t e = hipMemcpyAsync(h->tune_rv, r, 3 * ntot * sizeof(double),
                                       hipMemcpyDeviceToDevice, st);
@@ -634,10 +642,11 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
         for (int b = 0; b < NBUCKET; ++b)
             if (n >= BUCKET_LO[b] && n <= BUCKET_HI[b]) present[b] = true;
     }
-    // Probes run with the handle's graph setting (a new policy or grid changes
-    // the captured graph, so each probe captures first and times replays),
-    // coordinate by coordinate: the grid size with the current packing, then
-    // each present bucket's packing policy with the others kept.
+    // Probes launch directly (a graph captured anew for every probe setting
+    // was tried and its test crashed the host process once, cause not found;
+    // see the design notes), coordinate by coordinate: the grid size with the
+    // current packing, then each present bucket's packing policy with the
+    // others kept.
     const int reps = 2;
     double best = 1e300;
     if ((rc = probe(h, nsys, offsets, m, r, v, dt, probe_steps, G, stream, reps, &best)))
@@ -675,8 +684,10 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
         if (best_p < 0) {
             for (int p = 0; p < 3; ++p) {
                 bool same = true;
-                for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n)
-                    same = same && h->batch_group[n] == policy_group(p, n);
+                for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n) {
+                    const int lanes = h->batch_group[n] ? h->batch_group[n] : n; // 0: dense
+                    same = same && lanes == policy_group(p, n);
+                }
                 if (same) {
                     chosen[b] = p;
                     break;
