@@ -52,6 +52,12 @@ PLUMMER_HARVEST_STEPS = 2000  # harvest steps of the independent N = 4096 Plumme
 TRAFFIC_FILE = "profiles/k_pairs_cluster16384.traffic.json"
 
 
+def progress(msg):
+    """One line on stderr when a part of the benchmark ends (stdout carries
+    only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -168,10 +174,12 @@ def learned(torch, m, r, v, tau, steps, warmup, harvest_steps, oracle_step=None)
     torch.cuda.synchronize()
     t_harvest = time.perf_counter() - t0
     nrows = min(offered, cap)
+    progress(f"harvest done: {nrows} rows in {t_harvest:.1f} s")
     t0 = time.perf_counter()
     model, hist = h.mlp_fit(rows[:nrows], GUESS_DOMAIN, epochs=20, batch=4096, seed=1)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
+    progress(f"training done in {t_fit:.1f} s")
     del rows
     h.close()
 
@@ -193,6 +201,7 @@ def learned(torch, m, r, v, tau, steps, warmup, harvest_steps, oracle_step=None)
             torch.cuda.synchronize()
             walls[mode].append(time.perf_counter() - t0)
             stats[mode] = st
+        progress("learned: one plain and one learned run done")
     hp, hl = handles[GUESS_ANALYTIC], handles[GUESS_LEARNED]
     st_l = stats[GUESS_LEARNED]
     # the evaluations the plain starter takes in the network's domain (an
@@ -536,6 +545,7 @@ def main():
     st = lib.evolve(mt, rt, vt, tau, args.steps, stats=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    progress(f"timed block done: {wall * 1e3 / args.steps:.3f} ms per step")
 
     k_mean = st["iters_total"] / max(st["pair_solves"], 1)
     pair_ms = st["pair_kernel_ms"] / max(st["pair_launches"], 1)
@@ -595,16 +605,20 @@ def main():
     }
     if not args.no_schemes:
         out["schemes"] = schemes(lib, torch, m, r, v, tau)
+        progress("schemes done")
     if not args.no_hybrid:
         out["hybrid"] = hybrid(lib, torch, m, r, v, tau, args.steps, args.warmup)
+        progress("hybrid done")
     if not args.no_batched:
         out["batched"] = batched(lib, torch)
+        progress("batched ensemble done")
     # the oracle's full step (the CPU baseline) is the reference of the GPU
     # step's error over every row, for the plain and the learned starter
     cpu = None
     oracle_step = None
     if not args.no_cpu_baseline:
         cpu, oracle_step = cpu_baseline(m, r, v, tau)
+        progress("cpu baseline done")
     elif not args.no_parity:
         import oracle
         oracle_step = oracle.step(m, r, v, tau)
