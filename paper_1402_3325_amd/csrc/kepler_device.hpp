@@ -657,6 +657,43 @@ SAKURA_HD __attribute__((noinline)) PairCoef kepler_flow_default(double tau, dou
                     (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u)};
 }
 
+// The whole pair map of eq. (26) with the default parameters, for the split
+// of the step's drifts about the Kepler flow into two halves (cb = ca =
+// tau/2): the relative state (x, w) after the back-drift cb, the solve, and
+// the increments of the relative position and velocity less their starting
+// values, per unit mu, d = ((f - 1 - ca fdot) x + (g - tau - ca (gdot - 1)) w,
+// fdot x + (gdot - 1) w).  Formed here, the caller keeps nothing live across
+// the call (its copies of x and w in the callee-saved registers cost twelve
+// register moves per pair).  info as pack_info.  The arithmetic is that of
+// the caller's own form of the increments with ca = tau/2, which is exact.
+struct PairMap {
+    // position and velocity increments interleaved by component: (d0, d3),
+    // (d1, d4), (d2, d5), each pair formed from x_c and w_c alone, so that
+    // every result can take the return registers of the arguments it used
+    double dx0, dv0, dx1, dv1, dx2, dv2;
+    unsigned info;
+};
+SAKURA_HD __attribute__((noinline)) PairMap kepler_map_halves(double tau, double mu, double x0,
+                                                              double x1, double x2, double w0,
+                                                              double w1, double w2, double r0sq)
+{
+    constexpr KeplerParams kp{DEFAULT_TOL, DEFAULT_MAX_ITER};
+    NoGuess g;
+    const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    const double ca = 0.5 * tau;
+    const double a = fma(-ca, f.fdot, f.fm1);
+    const double b = fma(-ca, f.gdm1, f.gmt);
+    PairMap m;
+    m.dx0 = fma(a, x0, b * w0);
+    m.dv0 = fma(f.fdot, x0, f.gdm1 * w0);
+    m.dx1 = fma(a, x1, b * w1);
+    m.dv1 = fma(f.fdot, x1, f.gdm1 * w1);
+    m.dx2 = fma(a, x2, b * w2);
+    m.dv2 = fma(f.fdot, x2, f.gdm1 * w2);
+    m.info = ((unsigned)f.iters << 16) | (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u);
+    return m;
+}
+
 // Outcome of one pair's search packed for cheap accumulation: evaluations in
 // bits 16-31, a safeguarded step in bit 8, no convergence in bit 0.  Sums of
 // up to 64 of them keep the fields apart while every count of evaluations

@@ -200,7 +200,10 @@ __device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, 
 // the plain Kepler solve, the others the drift-kick-drift map of eq. (28),
 // dr = 0 and dv = tau a_ij, and the solve runs only in sub-steps where some
 // lane of the wavefront has a close pair.
-template <bool HIST, int MODE, bool DEFKP = false>
+// DEFKP: the solver copy with the default parameters built in; HALVES (with
+// DEFKP, modes 0 and 4, cb = ca = tau/2): the copy that also forms the
+// increments (kepler_map_halves), so that nothing stays live across the call.
+template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false>
 __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double cb, double ca, double G,
                                                 double e2, double e4,
@@ -246,6 +249,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
     const double t2 = tau * tau, mtau = -tau; // MODE 5
     const int nj = n - J * TILE; // valid j slots in this block
+    const int nj8 = 8 * nj, lane8 = 8 * lane;
 
     // Every lane solves a pair in every sub-step (lanes without one solve
     // tau = 0: one evaluation, converged, never safeguarded), so the outcomes
@@ -256,13 +260,18 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     GuessCount gc;                       // per wave
     unsigned dom_it = 0;                 // per lane
     int room = kep::DEFER_CAP;           // MODE 4: list slots left
-    bool any_collide = false;
+    unsigned long long coll_bits = 0; // lanes that met a zero separation (ballots, or-ed)
+    unsigned n_live = 0;              // HALVES: per lane, pairs solved
+    bool coll_lane = false;           // HALVES: per lane, a zero separation met
     float rmax = 0.0f;                   // per lane, HIST: largest relative Kepler residual
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
     for (int s = s0; s < s1; ++s) {
-        const int q = (lane + s) & (TILE - 1);
+        // q scaled by 8 (the byte offset of slot q in a row of doubles) is
+        // formed and tested directly: one vector operation less than q itself
+        const int q8 = (lane8 + 8 * s) & (8 * (TILE - 1));
+        const int q = q8 >> 3;
         // In harvest mode the particle data are read from LDS at every use and
         // the relative state is formed again after the solve (compiler-only
         // fences): its inlined policy's extra live state would otherwise push
@@ -270,7 +279,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         if (MODE == 3) asm volatile("" ::: "memory");
         const double mi = xi[6], mj = sj[6][q];
         const double msum = mi + mj;
-        const bool act = valid_i && (q < nj) && (msum > 0.0) &&
+        const bool act = valid_i && (q8 < nj8) && (msum > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         if constexpr (MODE == 5) {
             const double X0 = xi[0] - sj[0][q], X1 = xi[1] - sj[1][q], X2 = xi[2] - sj[2][q];
@@ -327,7 +336,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 }
             }
             n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
-            any_collide = any_collide || __builtin_amdgcn_ballot_w64(collide) != 0;
+            coll_bits |= __builtin_amdgcn_ballot_w64(collide);
             continue;
         }
         // relative state and the pair back-drift of eq. (17) by cb
@@ -361,7 +370,21 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 room = room > total ? room - total : 0;
             }
         }
-        if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
+        if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
+            // per-lane tallies (a ballot of these lane predicates costs two
+            // vector instructions each per sub-step; these cost at most one)
+            n_live += live ? 1u : 0u;
+            coll_lane = coll_lane | collide;
+            const kep::PairMap pm = kep::kepler_map_halves(live ? tau : 0.0, G * msum, x0, x1,
+                                                           x2, w0, w1, w2, live ? r0sq : 1.0);
+            d[0] = pm.dx0;
+            d[1] = pm.dx1;
+            d[2] = pm.dx2;
+            d[3] = pm.dv0;
+            d[4] = pm.dv1;
+            d[5] = pm.dv2;
+            info = pm.info;
+        } else if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
             const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
                 live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
             if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
@@ -423,11 +446,17 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         }
         info_sum += info;
         info_max = max(info_max, info);
-        n_solve += __popcll(__builtin_amdgcn_ballot_w64(live));
-        any_collide = any_collide || __builtin_amdgcn_ballot_w64(collide) != 0;
+        if constexpr (!(HALVES && !HIST && (MODE == 0 || MODE == 4))) {
+            n_solve += __popcll(__builtin_amdgcn_ballot_w64(live));
+            coll_bits |= __builtin_amdgcn_ballot_w64(collide);
+        }
         if (HIST && live) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
     }
 
+    if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
+        n_solve = wave_sum(n_live);
+        coll_bits = __builtin_amdgcn_ballot_w64(coll_lane);
+    }
     __syncthreads();
     const size_t cs = TILE; // component stride inside a partial
     double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
@@ -448,7 +477,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     const unsigned n_fb = wave_sum((info_sum >> 8) & 0xffu);
     const bool any_noconv = wave_sum(info_sum & 0xffu) != 0;
     if (MODE != 0 && MODE != 5) gc.dom_iters = wave_sum(dom_it);
-    const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (any_collide ? ST_COLLIDE : 0u);
+    const unsigned flags = (any_noconv ? ST_NOCONV : 0u) | (coll_bits ? ST_COLLIDE : 0u);
     const unsigned rbits = HIST ? wave_max(__float_as_uint(rmax)) : 0u;
     if (lane == 0) {
         slot_add(slots, blockIdx.x, n_solve, it_sum, n_fb, it_max);
@@ -781,15 +810,19 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
                     DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
                     const kep::GuessNet &net)
 {
-    // the plain solve with the default parameters built in, where they apply
+    // the plain solve with the default parameters built in, where they apply,
+    // and with the increments formed in the solver's copy where the drifts
+    // split into halves
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
+    const bool halves = !HIST && defkp && cb == ca && ca == 0.5 * dt;
 #define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, net
     switch (mode) {
     case 1:
         k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         break;
     case 2: // the network's starter: pairs of its domain go through k_deferred
-        if (defkp) k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        if (halves) k_pairs<HIST, 4, true, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        else if (defkp) k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         else k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, cb, ca, G, S, part, cnt,
                                                           slots, kp, step, net);
@@ -802,7 +835,8 @@ void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np,
         else k_pairs<HIST, 5><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         break;
     default:
-        if (defkp) k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        if (halves) k_pairs<HIST, 0, true, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        else if (defkp) k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
         else k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
     }
 #undef SAKURA_PAIR_ARGS
