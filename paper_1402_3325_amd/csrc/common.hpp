@@ -127,6 +127,7 @@ __global__ void k_fold_stats(const SlotStats *slots, DevCounters *c);
 
 struct sakura {
     int device = 0;
+    int cus = 256; // compute units of the device
     sakura_opts opts{};
     std::string err;
     double *state = nullptr; // [10][np]

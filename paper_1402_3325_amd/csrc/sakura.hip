@@ -203,8 +203,14 @@ __device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, 
 // DEFKP: the solver copy with the default parameters built in; HALVES (with
 // DEFKP, modes 0 and 4, cb = ca = tau/2): the copy that also forms the
 // increments (kepler_map_halves), so that nothing stays live across the call.
-template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false>
-__global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double tau,
+// SPLIT (every mode but 4, whose deferred-pair list belongs to one
+// wavefront): a workgroup of SPLIT wavefronts per
+// tile, all holding block I, wavefront w taking the sub-steps s = s0 + w,
+// s0 + w + SPLIT, ... with j-side slots of its own; at the end the
+// wavefronts' i-side and j-side sums are added in wavefront order.  For small
+// N, where the tiles alone would leave most of the SIMDs' wave slots empty.
+template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false, int SPLIT = 1>
+__global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double cb, double ca, double G,
                                                 double e2, double e4,
                                                 const double *__restrict__ S,
@@ -213,36 +219,50 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                                                 kep::KeplerParams kp, long long step,
                                                 const kep::GuessNet net)
 {
-    if (cnt->status) return; // an earlier failure: the call will report it
+    // an earlier failure: the call will report it (with SPLIT the workgroup
+    // takes one decision, as other workgroups may record a failure meanwhile)
+    if constexpr (SPLIT == 1) {
+        if (cnt->status) return;
+    } else {
+        __shared__ unsigned s_stop;
+        if (threadIdx.x == 0) s_stop = cnt->status;
+        __syncthreads();
+        if (s_stop) return;
+    }
     int I, J;
     tile_blocks(blockIdx.x, nb, I, J);
     const bool diag = (I == J);
-    const int lane = threadIdx.x;
+    static_assert(SPLIT == 1 || MODE != 4, "the deferred-pair list is one wavefront's");
+    const int lane = SPLIT == 1 ? (int)threadIdx.x : (int)threadIdx.x % TILE;
+    const int wv = SPLIT == 1 ? 0 : (int)threadIdx.x / TILE;
 
     const double *M = S;
     const double *V = S + 4 * (size_t)np;
     const double *XH = S + 7 * (size_t)np;
 
-    __shared__ double sj[7][TILE];  // x y z vx vy vz m of block J (read only)
-    __shared__ double sjs[6][TILE]; // j-side sums, by slot of block J
+    __shared__ double sj[7][TILE];          // x y z vx vy vz m of block J (read only)
+    __shared__ double sjs[SPLIT][6][TILE];  // j-side sums, by wavefront and slot of block J
+    __shared__ double sacc[SPLIT > 1 ? SPLIT - 1 : 1][6][TILE]; // i-side sums of wavefronts 1..
     __shared__ unsigned shist[HIST ? 32 : 1];
 
     const int jg = J * TILE + lane;
     const int ig = I * TILE + lane;
-    sj[0][lane] = XH[jg];
-    sj[1][lane] = XH[np + jg];
-    sj[2][lane] = XH[2 * (size_t)np + jg];
-    sj[3][lane] = V[jg];
-    sj[4][lane] = V[np + jg];
-    sj[5][lane] = V[2 * (size_t)np + jg];
-    sj[6][lane] = M[jg];
+    if (wv == 0) {
+        sj[0][lane] = XH[jg];
+        sj[1][lane] = XH[np + jg];
+        sj[2][lane] = XH[2 * (size_t)np + jg];
+        sj[3][lane] = V[jg];
+        sj[4][lane] = V[np + jg];
+        sj[5][lane] = V[2 * (size_t)np + jg];
+        sj[6][lane] = M[jg];
+    }
     // particle i and its sums stay in registers
     const double xi[7] = {XH[ig], XH[np + ig], XH[2 * (size_t)np + ig], V[ig], V[np + ig],
                           V[2 * (size_t)np + ig], M[ig]};
     double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sjs[c][lane] = 0.0;
-    if (HIST && lane < 32) shist[lane] = 0;
+    for (int c = 0; c < 6; ++c) sjs[wv][c][lane] = 0.0;
+    if (HIST && wv == 0 && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
     const double wgt_j = G * xi[6];
@@ -267,7 +287,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
-    for (int s = s0; s < s1; ++s) {
+    for (int s = s0 + wv; s < s1; s += SPLIT) {
         // q scaled by 8 (the byte offset of slot q in a row of doubles) is
         // formed and tested directly: one vector operation less than q itself
         const int q8 = (lane8 + 8 * s) & (8 * (TILE - 1));
@@ -301,9 +321,9 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
                 ai[3] = fma(ki, X0, ai[3]);
                 ai[4] = fma(ki, X1, ai[4]);
                 ai[5] = fma(ki, X2, ai[5]);
-                sjs[3][q] = fma(kj, X0, sjs[3][q]);
-                sjs[4][q] = fma(kj, X1, sjs[4][q]);
-                sjs[5][q] = fma(kj, X2, sjs[5][q]);
+                sjs[wv][3][q] = fma(kj, X0, sjs[wv][3][q]);
+                sjs[wv][4][q] = fma(kj, X1, sjs[wv][4][q]);
+                sjs[wv][5][q] = fma(kj, X2, sjs[wv][5][q]);
             } else {
                 // the Kepler map of eq. (26), as in MODE 0, for the close lanes
                 double d[6] = {0.0, 0.0, 0.0, kf * X0, kf * X1, kf * X2};
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     ai[c] = fma(wgt_i, d[c], ai[c]);
-                    sjs[c][q] = fma(-wgt_j, d[c], sjs[c][q]);
+                    sjs[wv][c][q] = fma(-wgt_j, d[c], sjs[wv][c][q]);
                 }
             }
             n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
@@ -442,7 +462,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             ai[c] = fma(wgt_i, d[c], ai[c]);
-            sjs[c][q] = fma(-wgt_j, d[c], sjs[c][q]);
+            sjs[wv][c][q] = fma(-wgt_j, d[c], sjs[wv][c][q]);
         }
         info_sum += info;
         info_max = max(info_max, info);
@@ -457,21 +477,40 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
         n_solve = wave_sum(n_live);
         coll_bits = __builtin_amdgcn_ballot_w64(coll_lane);
     }
+    if constexpr (SPLIT > 1) {
+        if (wv > 0)
+            for (int c = 0; c < 6; ++c) sacc[wv - 1][c][lane] = ai[c];
+    }
     __syncthreads();
-    const size_t cs = TILE; // component stride inside a partial
-    double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
-    if (diag) {
-        for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + sjs[c][lane];
-    } else {
-        double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
+    if (wv == 0) {
+        // the wavefronts' sums in wavefront order (SPLIT 1: the sums as they are)
+        double aj[6];
+#pragma unroll
         for (int c = 0; c < 6; ++c) {
-            pij[c * cs] = ai[c];
-            pji[c * cs] = sjs[c][lane];
+            aj[c] = sjs[0][c][lane];
+#pragma unroll
+            for (int w = 1; w < SPLIT; ++w) {
+                ai[c] += sacc[w - 1][c][lane];
+                aj[c] += sjs[w][c][lane];
+            }
+        }
+        const size_t cs = TILE; // component stride inside a partial
+        double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
+        if (diag) {
+            for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + aj[c];
+        } else {
+            double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
+            for (int c = 0; c < 6; ++c) {
+                pij[c * cs] = ai[c];
+                pji[c * cs] = aj[c];
+            }
         }
     }
 
-    // MODE 5 counts only the close lanes' solves
-    const unsigned trivial = MODE == 5 ? 0u : (unsigned)(TILE * (s1 - s0)) - (unsigned)n_solve;
+    // MODE 5 counts only the close lanes' solves; with SPLIT each wavefront
+    // counts the sub-steps it took
+    const int nsub_w = SPLIT == 1 ? s1 - s0 : (s1 - s0 - wv + SPLIT - 1) / SPLIT;
+    const unsigned trivial = MODE == 5 ? 0u : (unsigned)(TILE * nsub_w) - (unsigned)n_solve;
     const unsigned it_sum = wave_sum(info_sum >> 16) - trivial;
     const unsigned it_max = n_solve ? wave_max(info_max >> 16) : 0u;
     const unsigned n_fb = wave_sum((info_sum >> 8) & 0xffu);
@@ -490,7 +529,7 @@ __global__ __launch_bounds__(TILE, 4) void k_pairs(int n, int nb, int np, double
             net.defer_tiles[atomicAdd(&cnt->defer_ntiles, 1u)] = blockIdx.x;
         }
     }
-    if (HIST && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
+    if (HIST && wv == 0 && lane < 32) atomicAdd(&cnt->hist[lane], shist[lane]);
 }
 
 // The pairs that k_pairs listed (MODE 4): the list of one tile per wavefront;
@@ -803,56 +842,96 @@ __global__ __launch_bounds__(256) void k_energy_final(int ntiles, int nblk, doub
     }
 }
 
+// Wavefronts per tile for the plain mode: the tile kernel holds four
+// wavefronts per SIMD, and a launch of fewer than two rounds of tiles over all
+// of them leaves SIMDs idle or the last round ragged; splitting a tile's
+// sub-steps over 2 or 4 wavefronts fills them (at the cost of one combination
+// of the partial sums per tile).
+int pair_split(int ntiles, int cus)
+{
+    const int64_t slots = (int64_t)cus * 16; // 4 SIMDs x 4 wavefronts per CU
+    int split = 1;
+    while (split < 4 && (int64_t)ntiles * split < 2 * slots) split *= 2;
+    return split;
+}
+
+// One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one).
+template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false>
+void launch_tiles(int split, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
+                  double cb, double ca, double G, double e2, double e4, const double *S,
+                  double *part, DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp,
+                  long long step, const kep::GuessNet &net)
+{
+#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, net
+    if constexpr (MODE != 4) {
+        if (split == 4) {
+            k_pairs<HIST, MODE, DEFKP, HALVES, 4><<<ntiles, 4 * TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+            return;
+        }
+        if (split == 2) {
+            k_pairs<HIST, MODE, DEFKP, HALVES, 2><<<ntiles, 2 * TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+            return;
+        }
+    }
+    k_pairs<HIST, MODE, DEFKP, HALVES, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+#undef SAKURA_PAIR_ARGS
+}
+
 template <bool HIST>
-void launch_pairs_h(int mode, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
-                    double cb, double ca, double G, double e2, double e4, const double *S,
-                    double *part,
-                    DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
-                    const kep::GuessNet &net)
+void launch_pairs_h(int mode, int split, int ntiles, hipStream_t st, int n, int nb, int np,
+                    double dt, double cb, double ca, double G, double e2, double e4,
+                    const double *S, double *part, DevCounters *cnt, SlotStats *slots,
+                    kep::KeplerParams kp, long long step, const kep::GuessNet &net)
 {
     // the plain solve with the default parameters built in, where they apply,
     // and with the increments formed in the solver's copy where the drifts
     // split into halves
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
     const bool halves = !HIST && defkp && cb == ca && ca == 0.5 * dt;
-#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, net
+#define SAKURA_TILE_ARGS split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, \
+                         kp, step, net
     switch (mode) {
     case 1:
-        k_pairs<HIST, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        launch_tiles<HIST, 1>(SAKURA_TILE_ARGS);
         break;
     case 2: // the network's starter: pairs of its domain go through k_deferred
-        if (halves) k_pairs<HIST, 4, true, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
-        else if (defkp) k_pairs<HIST, 4, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
-        else k_pairs<HIST, 4><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        if (halves) launch_tiles<HIST, 4, true, true>(SAKURA_TILE_ARGS);
+        else if (defkp) launch_tiles<HIST, 4, true>(SAKURA_TILE_ARGS);
+        else launch_tiles<HIST, 4>(SAKURA_TILE_ARGS);
         k_deferred<<<std::min(ntiles, 1024), TILE, 0, st>>>(nb, np, dt, cb, ca, G, S, part, cnt,
                                                           slots, kp, step, net);
         break;
     case 3:
-        k_pairs<HIST, 3><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        launch_tiles<HIST, 3>(SAKURA_TILE_ARGS);
         break;
     case 5: // close-pair hybrid
-        if (defkp) k_pairs<HIST, 5, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
-        else k_pairs<HIST, 5><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        if (defkp) launch_tiles<HIST, 5, true>(SAKURA_TILE_ARGS);
+        else launch_tiles<HIST, 5>(SAKURA_TILE_ARGS);
         break;
     default:
-        if (halves) k_pairs<HIST, 0, true, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
-        else if (defkp) k_pairs<HIST, 0, true><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
-        else k_pairs<HIST, 0><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+        if constexpr (!HIST) {
+            if (halves) {
+                launch_tiles<false, 0, true, true>(SAKURA_TILE_ARGS);
+                break;
+            }
+        }
+        if (defkp) launch_tiles<HIST, 0, true>(SAKURA_TILE_ARGS);
+        else launch_tiles<HIST, 0>(SAKURA_TILE_ARGS);
     }
-#undef SAKURA_PAIR_ARGS
+#undef SAKURA_TILE_ARGS
 }
 
-void launch_pairs(bool hist, int mode, int ntiles, hipStream_t st, int n, int nb, int np,
+void launch_pairs(bool hist, int mode, int split, int ntiles, hipStream_t st, int n, int nb, int np,
                   double dt, double cb, double ca, double G, double e2, double e4,
                   const double *S, double *part,
                   DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
                   const kep::GuessNet &net)
 {
     if (hist)
-        launch_pairs_h<true>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+        launch_pairs_h<true>(mode, split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
                              slots, kp, step, net);
     else
-        launch_pairs_h<false>(mode, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+        launch_pairs_h<false>(mode, split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
                               slots, kp, step, net);
 }
 
@@ -984,6 +1063,10 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
         return SAKURA_EINVAL;
     sakura_t *h = new sakura();
     h->device = device;
+    if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        h->cus < 1)
+        h->cus = 256;
     if (opts) h->opts = *opts;
     if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = kep::DEFAULT_TOL;
     if (h->opts.max_iter <= 0) h->opts.max_iter = kep::DEFAULT_MAX_ITER;
@@ -1102,6 +1185,7 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
     double pair_ms = 0.0;
 
     const int ntiles = nb * (nb + 1) / 2;
+    const int split = pair_split(ntiles, h->cus);
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
     int mode = sk::guess_mode(h, &net);
@@ -1139,7 +1223,7 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
             const size_t slot = timing ? (size_t)(e % ring) : 0;
             if (timing && e >= ring && (rc = read_pair_timing(h, slot, &pair_ms))) return rc;
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * slot], st));
-            launch_pairs(h->opts.histogram != 0, mode, ntiles, st, (int)n, nb, np, g.t, g.cb,
+            launch_pairs(h->opts.histogram != 0, mode, split, ntiles, st, (int)n, nb, np, g.t, g.cb,
                          g.ca, G, e2, e4, buf.state, buf.part, buf.cnt, buf.slots, kp, s, net);
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * slot], st));
             k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, buf.state,

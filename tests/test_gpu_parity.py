@@ -96,6 +96,34 @@ def test_parity_plummer_4096_full(torch, lib, oracle):
         r, v = ro, vo
 
 
+@pytest.mark.parametrize("n", [1000, 6000, 9000])
+def test_parity_split_tiles(torch, lib, oracle, n):
+    """Where the tiles alone would leave most wave slots of the device empty,
+    each tile's sub-steps are split over 2 or 4 wavefronts (on 256 compute
+    units: 4 at n = 1000, 2 at n = 6000, 1 at n = 9000).  Every row against
+    the oracle; the exact number of pair solves; and the diagnostic copy, which
+    splits alike, bitwise equal, with its per-pair histogram matching the
+    packed counters."""
+    from paper_1402_3325_amd.sakura import Sakura
+    m, r, v, tau = workloads.cluster(n_stars=n - 1, rng=np.random.default_rng(7000 + n))
+    rg, vg, st = gpu_step(torch, lib, m, r, v, tau, stats=True)
+    ro, vo = oracle.step(m, r, v, tau)
+    er, ev = step_error(rg, vg, ro, vo, r, v)
+    print(f"n={n} err {er:.2e} {ev:.2e}")
+    assert er <= TOL and ev <= TOL
+    assert st["pair_solves"] == n * (n - 1) // 2
+    hd = Sakura(0, histogram=True)
+    try:
+        rd, vd, sd = gpu_step(torch, hd, m, r, v, tau, stats=True)
+    finally:
+        hd.close()
+    hist = np.array(sd["hist"], dtype=np.int64)
+    assert np.array_equal(rd, rg) and np.array_equal(vd, vg)
+    assert sd["pair_solves"] == st["pair_solves"] == hist.sum()
+    assert sd["iters_total"] == st["iters_total"] == int(np.sum(np.arange(32) * hist))
+    assert sd["iters_max"] == st["iters_max"]
+
+
 def _cluster_rows(m, r, rng, count=64, tight=32):
     """Rows to sample in a cluster: the central mass (row 0), the `tight`
     stars closest to a neighbour (members of the tightest binaries) with those
