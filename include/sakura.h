@@ -204,18 +204,30 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
 
 /* Packing of batched systems: policy 0 gives a system of n particles n lanes
  * (dense), 1 rounds n up to even, 2 to a power of two; waves_per_cu sizes the
- * persistent grid; use_graph = 0 launches the kernels directly. */
+ * persistent grid; use_graph = 0 launches the kernels directly (the three
+ * launch widths on three streams).  Resets the wavefronts per item to their
+ * default (sakura_batch_set_width).  A new handle packs with policy 0, 16
+ * wavefronts per compute unit and the graph. */
 int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_graph);
 
 /* Lanes used by systems of exactly n particles (n <= lanes <= 64). */
 int sakura_batch_set_group(sakura_t *h, int n, int lanes);
 
+/* Wavefronts per work item (1, 2 or 4) for systems of exactly n particles:
+ * the wavefronts of an item hold the same systems and take every first,
+ * second or fourth sub-step of the pair schedule, which shortens the item's
+ * sequential chain.  The default (also after sakura_batch_set_policy) is 4.
+ * EINVAL for n outside [1, 64] or another count. */
+int sakura_batch_set_width(sakura_t *h, int n, int waves);
+
 /* Tune the packing on this ensemble (scratch copies; r and v are not
  * modified): the grid size (4, 8 or 16 wavefronts per compute unit), then for
  * each size bucket the ensemble has systems in (1-8, 9-16, 17-32, 33-64
- * particles) the lane policy of sakura_batch_set_policy, one coordinate at a
- * time.  Each probe runs probe_steps steps with direct launches (no graph)
- * and takes the least of two timed calls after a warm-up call.  The best settings stay on the handle and are recorded in
+ * particles) the lane policy of sakura_batch_set_policy and then the
+ * wavefronts per item (1, 2 or 4), one coordinate at a time.  Each probe runs
+ * probe_steps steps with direct launches (no graph; the three launch widths
+ * side by side on three streams, as in the graph) and takes the least of two
+ * timed calls after a warm-up call.  The best settings stay on the handle and are recorded in
  * its packing table under (gfx architecture, compute units, bucket); the
  * least probe time goes to *best_ms (may be NULL).  If a probe fails, its
  * error is returned and the handle keeps the settings it had. */
@@ -224,8 +236,8 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
                           int64_t probe_steps, double G, void *stream, double *best_ms);
 
 /* The packing table as a text file (one line per entry: arch, compute units,
- * bucket 0-3, policy 0-2, wavefronts per compute unit; '#' lines are
- * comments).  Load merges the file's entries into the handle's table and
+ * bucket 0-3, policy 0-2, wavefronts per compute unit, wavefronts per item
+ * 1/2/4; '#' lines are comments).  Load merges the file's entries into the handle's table and
  * applies those of the handle's device; EINVAL for an unreadable or malformed
  * file (the table is then unchanged). */
 int sakura_batch_table_save(const sakura_t *h, const char *path);

@@ -19,12 +19,14 @@
 // One wavefront takes about 1.2 us per sub-step (the solve's dependency chain
 // with no other work to hide it), and a system of n particles needs about n/2
 // sequential sub-steps per step, so the largest systems set the length of
-// the launch.  Items of more than 16 lanes therefore go to workgroups of two
-// (17..32 lanes) or four (33..64) wavefronts that hold the same particles and
-// take every second or fourth sub-step, each with its own j-side LDS slots;
-// the partial sums are combined in a fixed order once per step, so all the
-// wavefronts of a group carry bitwise the same state.  The three launches run
-// as parallel branches of the captured graph.
+// the launch.  Items of larger systems therefore go to workgroups of two or
+// four wavefronts that hold the same particles and take every second or
+// fourth sub-step, each with its own j-side LDS slots; the partial sums are
+// combined in a fixed order once per step, so all the wavefronts of a group
+// carry bitwise the same state.  The wavefronts per item follow the system
+// size (by default four; per size bucket as tuned or set).  The three launch widths run side by side: as parallel
+// branches of the captured graph, or, launched directly, on three streams
+// joined by events.
 #include "common.hpp"
 
 #include <algorithm>
@@ -311,6 +313,28 @@ namespace {
 
 // Lanes per system of size n under each packing policy: 0 dense (n lanes),
 // 1 even (n rounded up to even), 2 power of two.
+// Wavefronts per work item for systems of n particles: the handle's setting,
+// else four (on the 4096-system benchmark ensemble four for every size with
+// 16 wavefronts per CU measured 79 G pair-solves/s, against 66-70 G for four,
+// two and one by size class and 8 or 16 per CU).
+int batch_width(const sakura_t *h, int n)
+{
+    const int w = h->batch_width[n];
+    return w ? w : 4;
+}
+
+// The streams and events of the side-by-side launches (created once).
+int branch_streams(sakura_t *h)
+{
+    if (!h->capture_stream)
+        SAKURA_HIP(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    for (hipStream_t *sp : {&h->capture_stream2, &h->capture_stream3})
+        if (!*sp) SAKURA_HIP(h, hipStreamCreateWithFlags(sp, hipStreamNonBlocking));
+    for (hipEvent_t *ep : {&h->graph_fork, &h->graph_join, &h->graph_join2})
+        if (!*ep) SAKURA_HIP(h, hipEventCreateWithFlags(ep, hipEventDisableTiming));
+    return SAKURA_OK;
+}
+
 int policy_group(int policy, int n)
 {
     switch (policy) {
@@ -380,11 +404,20 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         k = e;
     }
     const int nitems = (int)(items.size() / 4);
-    int nw[3] = {0, 0, 0}; // items of 4, 2, 1 wavefronts (sorted by L, largest first)
-    for (int k = 0; k < nitems; ++k) {
-        const int L = items[4 * k + 2];
-        ++nw[L > TILE / 2 ? 0 : (L > TILE / 4 ? 1 : 2)];
-    }
+    // items of 4, 2 and 1 wavefronts, in that order, each group in size order
+    int nw[3] = {0, 0, 0};
+    std::vector<int> grouped;
+    grouped.reserve(items.size());
+    for (int cls = 0; cls < 3; ++cls)
+        for (int k = 0; k < nitems; ++k) {
+            const int *it = &items[4 * (size_t)k];
+            const int n = (int)(offsets[order[(size_t)it[0]] + 1] - offsets[order[(size_t)it[0]]]);
+            const int w = batch_width(h, n);
+            if ((w == 4 ? 0 : (w == 2 ? 1 : 2)) != cls) continue;
+            grouped.insert(grouped.end(), it, it + 4);
+            ++nw[cls];
+        }
+    items.swap(grouped);
     h->host_work.assign(items.begin(), items.end());
     h->host_work.insert(h->host_work.end(), order.begin(), order.end());
 
@@ -444,12 +477,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
             (void)hipGraphDestroy(h->graph);
             h->graph = nullptr;
         }
-        if (!h->capture_stream)
-            SAKURA_HIP(h, hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
-        for (hipStream_t *sp : {&h->capture_stream2, &h->capture_stream3})
-            if (!*sp) SAKURA_HIP(h, hipStreamCreateWithFlags(sp, hipStreamNonBlocking));
-        for (hipEvent_t *ep : {&h->graph_fork, &h->graph_join, &h->graph_join2})
-            if (!*ep) SAKURA_HIP(h, hipEventCreateWithFlags(ep, hipEventDisableTiming));
+        if ((rc = branch_streams(h))) return rc;
         // recorded by a function so that a failed record still ends the
         // capture (the stream would otherwise stay in capture mode)
         auto record = [&]() -> int {
@@ -489,10 +517,21 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     if (use_graph) {
         SAKURA_HIP(h, hipGraphLaunch(h->graph_exec, st));
     } else {
+        // the three widths side by side on st and two private streams, as in
+        // the graph: forked from st after the counters are cleared, joined
+        // back before the export
+        if ((rc = branch_streams(h))) return rc;
         k_clear<<<1, NSLOT, 0, st>>>(h->cnt, h->slots);
-        const hipStream_t bst[3] = {st, st, st};
+        SAKURA_HIP(h, hipEventRecord(h->graph_fork, st));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
+        SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
+        const hipStream_t bst[3] = {st, h->capture_stream2, h->capture_stream3};
         launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
                      h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
+        SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
+        SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
+        SAKURA_HIP(h, hipStreamWaitEvent(st, h->graph_join, 0));
+        SAKURA_HIP(h, hipStreamWaitEvent(st, h->graph_join2, 0));
         k_batch_export<<<eblocks, 256, 0, st>>>(ntot, h->batch_state, r, v, h->cnt);
         k_fold_stats<<<1, NSLOT, 0, st>>>(h->slots, h->cnt);
         SAKURA_HIP(h, hipGetLastError());
@@ -525,7 +564,10 @@ int sakura_batch_set_policy(sakura_t *h, int policy, int waves_per_cu, int use_g
 {
     if (!h || policy < 0 || policy > 2 || waves_per_cu < 1 || waves_per_cu > 32)
         return SAKURA_EINVAL;
-    for (int n = 1; n <= sk::TILE; ++n) h->batch_group[n] = policy_group(policy, n);
+    for (int n = 1; n <= sk::TILE; ++n) {
+        h->batch_group[n] = policy_group(policy, n);
+        h->batch_width[n] = 0;
+    }
     h->batch_waves_per_cu = waves_per_cu;
     h->batch_no_graph = !use_graph;
     return SAKURA_OK;
@@ -546,6 +588,10 @@ void set_bucket_policy(sakura_t *h, int b, int policy)
 {
     for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n) h->batch_group[n] = policy_group(policy, n);
 }
+void set_bucket_width(sakura_t *h, int b, int width)
+{
+    for (int n = BUCKET_LO[b]; n <= BUCKET_HI[b]; ++n) h->batch_width[n] = width;
+}
 
 // The device's identity in the table: its gfx architecture and compute units.
 void device_identity(int device, std::string &arch, int &cus)
@@ -561,8 +607,9 @@ void device_identity(int device, std::string &arch, int &cus)
     }
 }
 
-// Apply the handle's table entries for this device: per-bucket policy and the
-// grid size (the grid of the last entry that names one).
+// Apply the handle's table entries for this device: per-bucket policy and
+// wavefronts per item, and the grid size (the grid of the last entry that
+// names one).
 void apply_table(sakura_t *h)
 {
     std::string arch;
@@ -571,6 +618,7 @@ void apply_table(sakura_t *h)
     for (const auto &e : h->batch_table)
         if (e.arch == arch && e.cus == cus && e.bucket >= 0 && e.bucket < NBUCKET) {
             set_bucket_policy(h, e.bucket, e.policy);
+            set_bucket_width(h, e.bucket, e.width);
             h->batch_waves_per_cu = e.waves_per_cu;
         }
 }
@@ -627,11 +675,13 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
     int rc;
     if ((rc = grow(h, &h->tune_rv, &h->cap_tune, 6 * ntot))) return rc;
     // a failed probe leaves the handle's batch settings as they were
-    int saved_group[TILE + 1];
+    int saved_group[TILE + 1], saved_width[TILE + 1];
     std::memcpy(saved_group, h->batch_group, sizeof(saved_group));
+    std::memcpy(saved_width, h->batch_width, sizeof(saved_width));
     const int saved_waves = h->batch_waves_per_cu;
     auto restore = [&](int code) {
         std::memcpy(h->batch_group, saved_group, sizeof(saved_group));
+        std::memcpy(h->batch_width, saved_width, sizeof(saved_width));
         h->batch_waves_per_cu = saved_waves;
         return code;
     };
@@ -661,7 +711,7 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
         if (t < best) best = t;
         else h->batch_waves_per_cu = keep;
     }
-    int chosen[NBUCKET] = {-1, -1, -1, -1};
+    int chosen[NBUCKET] = {-1, -1, -1, -1}, chosen_w[NBUCKET] = {0, 0, 0, 0};
     for (int b = 0; b < NBUCKET; ++b) {
         if (!present[b]) continue;
         int keep_group[TILE + 1];
@@ -679,6 +729,22 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
             }
         }
         std::memcpy(h->batch_group, keep_group, sizeof(keep_group));
+        // then the wavefronts per item, with the chosen lanes
+        const int keep_w = batch_width(h, BUCKET_LO[b]);
+        int best_w = keep_w;
+        for (const int w : {1, 2, 4}) {
+            if (w == keep_w) continue;
+            set_bucket_width(h, b, w);
+            double t;
+            if ((rc = probe(h, nsys, offsets, m, r, v, dt, probe_steps, G, stream, reps, &t)))
+                return restore(rc);
+            if (t < best) {
+                best = t;
+                best_w = w;
+            }
+        }
+        set_bucket_width(h, b, best_w);
+        chosen_w[b] = best_w;
         // the policy the bucket holds now (probed or kept)
         chosen[b] = best_p;
         if (best_p < 0) {
@@ -706,9 +772,12 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
             if (e.arch == arch && e.cus == cus && e.bucket == b) {
                 e.policy = chosen[b];
                 e.waves_per_cu = h->batch_waves_per_cu;
+                e.width = chosen_w[b];
                 found = true;
             }
-        if (!found) h->batch_table.push_back({arch, cus, b, chosen[b], h->batch_waves_per_cu});
+        if (!found)
+            h->batch_table.push_back(
+                {arch, cus, b, chosen[b], h->batch_waves_per_cu, chosen_w[b]});
     }
     if (best_ms) *best_ms = best;
     return SAKURA_OK;
@@ -720,10 +789,10 @@ int sakura_batch_table_save(const sakura_t *h, const char *path)
     FILE *f = std::fopen(path, "w");
     if (!f) return SAKURA_EINVAL;
     std::fprintf(f, "# sakura batched packing table: arch cus bucket(1-8,9-16,17-32,33-64) "
-                    "policy(0 dense,1 even,2 pow2) waves_per_cu\n");
+                    "policy(0 dense,1 even,2 pow2) waves_per_cu wavefronts_per_item(1,2,4)\n");
     for (const auto &e : h->batch_table)
-        std::fprintf(f, "%s %d %d %d %d\n", e.arch.c_str(), e.cus, e.bucket, e.policy,
-                     e.waves_per_cu);
+        std::fprintf(f, "%s %d %d %d %d %d\n", e.arch.c_str(), e.cus, e.bucket, e.policy,
+                     e.waves_per_cu, e.width);
     return std::fclose(f) == 0 ? SAKURA_OK : SAKURA_EINVAL;
 }
 
@@ -739,13 +808,14 @@ int sakura_batch_table_load(sakura_t *h, const char *path)
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[128];
-        int cus, b, p, w;
-        if (std::sscanf(line, "%127s %d %d %d %d", arch, &cus, &b, &p, &w) != 5 || b < 0 ||
-            b >= NBUCKET || p < 0 || p > 2 || w < 1 || w > 32) {
+        int cus, b, p, w, iw;
+        if (std::sscanf(line, "%127s %d %d %d %d %d", arch, &cus, &b, &p, &w, &iw) != 6 ||
+            b < 0 || b >= NBUCKET || p < 0 || p > 2 || w < 1 || w > 32 ||
+            (iw != 1 && iw != 2 && iw != 4)) {
             bad = 1;
             break;
         }
-        rows.push_back({arch, cus, b, p, w});
+        rows.push_back({arch, cus, b, p, w, iw});
     }
     std::fclose(f);
     if (bad) return sk::fail(h, SAKURA_EINVAL, std::string("malformed table line in ") + path);
@@ -766,6 +836,14 @@ int sakura_batch_set_group(sakura_t *h, int n, int lanes)
 {
     if (!h || n < 1 || n > sk::TILE || lanes < n || lanes > sk::TILE) return SAKURA_EINVAL;
     h->batch_group[n] = lanes;
+    return SAKURA_OK;
+}
+
+int sakura_batch_set_width(sakura_t *h, int n, int waves)
+{
+    if (!h || n < 1 || n > sk::TILE || (waves != 1 && waves != 2 && waves != 4))
+        return SAKURA_EINVAL;
+    h->batch_width[n] = waves;
     return SAKURA_OK;
 }
 

@@ -157,16 +157,17 @@ struct sakura {
     hipGraphExec_t graph_exec = nullptr;
     std::string graph_key;
     int batch_group[65] = {0}; // lanes per system of each size (0: the size itself)
+    int batch_width[65] = {0}; // wavefronts per work item by system size (0: the default)
     double *tune_rv = nullptr; // autotuner scratch copies of r, v
     int64_t cap_tune = 0;
-    int batch_waves_per_cu = 8;
+    int batch_waves_per_cu = 16;
     int batch_no_graph = 0;
     // packing table: per (gfx arch, compute units, system-size bucket) the
     // lane policy and grid size that sakura_autotune_batch chose or a table
     // file supplied
     struct BatchTuneEntry {
         std::string arch;
-        int cus, bucket, policy, waves_per_cu;
+        int cus, bucket, policy, waves_per_cu, width;
     };
     std::vector<BatchTuneEntry> batch_table;
     // learned starter

@@ -133,6 +133,8 @@ def load_library():
     L.sakura_batch_set_policy.restype = ctypes.c_int
     L.sakura_batch_set_group.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.sakura_batch_set_group.restype = ctypes.c_int
+    L.sakura_batch_set_width.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    L.sakura_batch_set_width.restype = ctypes.c_int
     L.sakura_autotune_batch.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P, P, P,
                                         P, ctypes.c_int64, ctypes.c_double, P,
                                         ctypes.POINTER(ctypes.c_double)]
@@ -312,6 +314,14 @@ class Sakura:
         rc = self._lib.sakura_batch_set_policy(self._h, policy, waves_per_cu, int(bool(use_graph)))
         if rc != OK:
             self._raise(rc)
+
+    def batch_set_group(self, n: int, lanes: int):
+        """Lanes used by systems of exactly n particles."""
+        self._ok(self._lib.sakura_batch_set_group(self._h, int(n), int(lanes)))
+
+    def batch_set_width(self, n: int, waves: int):
+        """Wavefronts per work item (1, 2 or 4) for systems of exactly n particles."""
+        self._ok(self._lib.sakura_batch_set_width(self._h, int(n), int(waves)))
 
     def autotune_batch(self, offsets, m, r, v, dt, probe_steps: int = 8, G: float = 1.0):
         """Pick the fastest packing policy and grid size for this ensemble

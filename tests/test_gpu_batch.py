@@ -84,8 +84,8 @@ def test_batch_matches_oracle_every_step(torch, lib, oracle, policy):
 def test_in_kernel_steps_equal_single_steps(torch, lib, policy):
     """One launch of k steps (the state carried in registers, eq. 27a redone in
     place) against k launches of one step each: bitwise equal, for every
-    packing policy and for items of one, two and four wavefronts (SIZES spans
-    1..64 particles)."""
+    packing policy (SIZES spans 1..64 particles; items of the default four
+    wavefronts here, of one and two in the width test)."""
     lib.batch_set_policy(policy, 8, True)
     try:
         off, m, r, v, tau = small_ensemble(SIZES, seed=31)
@@ -97,6 +97,38 @@ def test_in_kernel_steps_equal_single_steps(torch, lib, policy):
         assert torch.equal(rk, r1) and torch.equal(vk, v1)
     finally:
         lib.batch_set_policy(0, 8, True)
+
+
+@pytest.mark.parametrize("width", [1, 2, 4])
+def test_item_widths_match_oracle_and_single_steps(torch, lib, oracle, width):
+    """Every system size (1..64) on items of `width` wavefronts: one step
+    against the oracle per system at 1e-12, and one launch of 5 steps bitwise
+    equal to 5 launches of one step (each launch with its three widths side by
+    side, once from the graph and once launched directly)."""
+    off, m, r, v, tau = small_ensemble(SIZES, seed=77 + width)
+    for use_graph in (True, False):
+        lib.batch_set_policy(0, 8, use_graph)
+        try:
+            for n in range(1, 65):
+                lib.batch_set_width(n, width)
+            mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
+            lib.batch_evolve(off, mt, rt, vt, dtt, 1)
+            rg, vg = rt.cpu().numpy(), vt.cpu().numpy()
+            for s in range(len(SIZES)):
+                a, b = off[s], off[s + 1]
+                ro, vo = oracle.step(m[a:b], r[a:b], v[a:b], tau[s])
+                er, ev = sys_error(rg[a:b], vg[a:b], ro, vo, r[a:b], v[a:b])
+                assert er <= TOL and ev <= TOL, (width, use_graph, s, SIZES[s], er, ev)
+            mt, rk, vk, dtt = _dev(torch, m, r, v, tau)
+            lib.batch_evolve(off, mt, rk, vk, dtt, 5)
+            r1, v1 = _dev(torch, r, v)
+            for _ in range(5):
+                lib.batch_evolve(off, mt, r1, v1, dtt, 1)
+            assert torch.equal(rk, r1) and torch.equal(vk, v1), (width, use_graph)
+        finally:
+            lib.batch_set_policy(0, 8, True)
+    with pytest.raises(Exception):
+        lib.batch_set_width(16, 3)
 
 
 def test_in_kernel_steps_match_oracle(torch, lib, oracle):
@@ -318,7 +350,7 @@ def test_autotune_table_round_trip(torch, tmp_path):
         assert all(x[0] == arch and int(x[1]) == torch.cuda.get_device_properties(0)
                    .multi_processor_count for x in rows)
         bad = tmp_path / "bad.txt"
-        bad.write_text("gfx950 256 7 0 8\n")
+        bad.write_text("gfx950 256 7 0 8 1\n")
         with pytest.raises(SakuraError) as e:
             hb.batch_table_load(bad)
         assert e.value.code == EINVAL
@@ -335,31 +367,36 @@ def test_autotune_table_round_trip(torch, tmp_path):
 
 
 def test_batch_table_load_applies_each_bucket(torch, tmp_path):
-    """A packing table file for this device (one lane policy per size bucket)
-    loaded into a fresh handle packs the ensemble as the equivalent per-size
-    lane groups set by hand: bitwise equal results.  Entries of another
+    """A packing table file for this device (one lane policy and one item
+    width per size bucket) loaded into a fresh handle packs the ensemble as the
+    equivalent per-size lane groups and widths set by hand: bitwise equal
+    results.  Entries of another
     architecture are kept but not applied, and a malformed file is refused."""
     from paper_1402_3325_amd.sakura import Sakura, SakuraError, EINVAL
     off, m, r, v, tau = small_ensemble([5, 7, 9, 13, 20, 27, 40, 63, 3, 3], seed=61)
     props = torch.cuda.get_device_properties(0)
     arch, cus = props.gcnArchName.split(":")[0], props.multi_processor_count
     policy = {0: 2, 1: 1, 2: 2, 3: 1}  # bucket -> pow2 / even lanes
+    width = {0: 2, 1: 1, 2: 4, 3: 2}   # bucket -> wavefronts per item
     path = tmp_path / "table.txt"
-    path.write_text("# test table\n" + "".join(f"{arch} {cus} {b} {p} 8\n" for b, p in policy.items())
-                    + "gfx000 1 3 0 4\n")
+    path.write_text("# test table\n" + "".join(f"{arch} {cus} {b} {p} 8 {width[b]}\n"
+                                               for b, p in policy.items())
+                    + "gfx000 1 3 0 4 1\n")
     ha, hb = Sakura(0), Sakura(0)
     try:
         bad = tmp_path / "bad.txt"
-        bad.write_text(f"{arch} {cus} 7 0 8\n")
-        with pytest.raises(SakuraError) as e:
-            ha.batch_table_load(bad)
-        assert e.value.code == EINVAL
+        for line in (f"{arch} {cus} 7 0 8 1\n", f"{arch} {cus} 1 0 8 3\n", f"{arch} {cus} 1 0 8\n"):
+            bad.write_text(line)
+            with pytest.raises(SakuraError) as e:
+                ha.batch_table_load(bad)
+            assert e.value.code == EINVAL
         ha.batch_table_load(path)
         bounds = {0: (1, 8), 1: (9, 16), 2: (17, 32), 3: (33, 64)}
         for b, (lo, hi) in bounds.items():
             for n in range(lo, hi + 1):
                 L = n + (n & 1) if policy[b] == 1 else 1 << (n - 1).bit_length()
-                hb._ok(hb._lib.sakura_batch_set_group(hb._h, n, L))
+                hb.batch_set_group(n, L)
+                hb.batch_set_width(n, width[b])
         out = []
         for h in (ha, hb):
             mt, rt, vt, dtt = _dev(torch, m, r, v, tau)
@@ -369,7 +406,7 @@ def test_batch_table_load_applies_each_bucket(torch, tmp_path):
         saved = tmp_path / "saved.txt"
         ha.batch_table_save(saved)
         rows = [ln.split() for ln in saved.read_text().splitlines() if not ln.startswith("#")]
-        assert len(rows) == 5 and ["gfx000", "1", "3", "0", "4"] in rows
+        assert len(rows) == 5 and ["gfx000", "1", "3", "0", "4", "1"] in rows
     finally:
         ha.close()
         hb.close()
