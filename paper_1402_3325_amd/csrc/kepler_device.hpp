@@ -304,13 +304,29 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
     double G3 = fma(d, e.G2, e.G3);
     double G2 = fma(d, e.G1, e.G2);
     double G1 = fma(d, e.G0, e.G1);
-    if (TIER != 2 || !SAKURA_WAVE_ALL(!done || ads <= 0x1p-28 * asn)) {
+    // order of the shift that suffices on every lane that takes the root: the
+    // first, else the second, else the third.  After a Newton step on every
+    // lane (|ds| <= 2^-23 |s - ds|, all lanes done) the second always does,
+    // and the test for the first is a plain comparison on every lane.
+    bool first = false, second = false;
+    if (TIER == 2) {
+        if (nt) {
+            // (scaled on the other side than below: the two comparisons stay
+            // apart, each next to its ballot)
+            first = SAKURA_WAVE_ALL(0x1p28 * ads <= asn);
+            second = true;
+        } else {
+            first = SAKURA_WAVE_ALL(!done || ads <= 0x1p-28 * asn);
+            second = first || SAKURA_WAVE_ALL(!done || ads <= 0x1p-18 * asn);
+        }
+    }
+    if (!first) {
         const double d2 = 0.5 * d * d;
         const double mbG1 = -beta * e.G1;
         G3 = fma(d2, e.G1, G3);
         G2 = fma(d2, e.G0, G2);
         G1 = fma(d2, mbG1, G1);
-        if (TIER != 2 || !SAKURA_WAVE_ALL(!done || ads <= 0x1p-18 * asn)) {
+        if (!second) {
             const double d3 = d2 * d * (1.0 / 3.0);
             G3 = fma(d3, e.G0, G3);
             G2 = fma(d3, mbG1, G2);

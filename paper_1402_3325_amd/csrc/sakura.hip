@@ -275,14 +275,15 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     // tau = 0: one evaluation, converged, never safeguarded), so the outcomes
     // are summed over all lanes and the trivial ones taken off at the end.
     unsigned info_sum = 0, info_max = 0; // per lane: sum and maximum of kep::pack_info
-    unsigned long long n_solve = 0;      // per wave (ballot count)
+    unsigned long long n_solve = 0;      // per wave: pairs solved (ballot counts, or with
+                                         // HALVES the per-lane tallies summed at the end)
     unsigned long long n_kick = 0;       // per wave, MODE 5
     GuessCount gc;                       // per wave
     unsigned dom_it = 0;                 // per lane
     int room = kep::DEFER_CAP;           // MODE 4: list slots left
-    unsigned long long coll_bits = 0; // lanes that met a zero separation (ballots, or-ed)
-    unsigned n_live = 0;              // HALVES: per lane, pairs solved
-    bool coll_lane = false;           // HALVES: per lane, a zero separation met
+    unsigned long long coll_bits = 0;    // per wave: lanes that met a zero separation
+    unsigned n_live = 0;                 // HALVES: per lane, pairs solved
+    bool coll_lane = false;              // HALVES: per lane, a zero separation met
     float rmax = 0.0f;                   // per lane, HIST: largest relative Kepler residual
     __syncthreads();
 
