@@ -147,6 +147,36 @@ def batched(lib, torch, steps=256):
                               "tol": 1e-12}}
 
 
+def plummer4096(lib, torch, steps=64, warmup=16):
+    """The equal-mass Plummer sphere of N = 4096 (tau = 1/1024, 64 steps): the
+    smaller single-system workload, where the tile kernel splits each tile's
+    sub-steps over several wavefronts to fill the device.  Its first step is
+    compared with the oracle's over every row."""
+    import oracle
+    from paper_1402_3325_amd import workloads
+    m, r, v, tau, _ = workloads.config(1)
+    n = len(m)
+    pairs = n * (n - 1) // 2
+    mt, rt, vt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (m, r, v))
+    r1, v1 = rt.clone(), vt.clone()
+    lib.evolve(mt, r1, v1, tau, 1)
+    ro, vo = oracle.step(m, r, v, tau)
+    er, ev = step_error(r1.cpu().numpy(), v1.cpu().numpy(), ro, vo, r, v)
+    lib.evolve(mt, rt, vt, tau, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = lib.evolve(mt, rt, vt, tau, steps, stats=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pair_ms = st["pair_kernel_ms"] / max(st["pair_launches"], 1)
+    return {"value": pairs * steps / wall, "unit": "pair-solves/s",
+            "workload": f"Plummer sphere N={n}, tau=1/1024, {steps} steps",
+            "ms_per_step": wall * 1e3 / steps, "pair_kernel_ms": pair_ms,
+            "kernel_rate": pairs / (pair_ms * 1e-3),
+            "mean_kepler_iters": st["iters_total"] / max(st["pair_solves"], 1),
+            "err_vs_oracle": {"err_r": er, "err_v": ev, "rows": int(n), "tol": 1e-12}}
+
+
 def learned(torch, m, r, v, tau, steps, warmup, harvest_steps, oracle_step=None):
     """The learned Kepler starter on the same workload.  Rows are harvested
     with the plain starter from independent runs of the Plummer sphere and of
@@ -606,6 +636,9 @@ def main():
     if not args.no_schemes:
         out["schemes"] = schemes(lib, torch, m, r, v, tau)
         progress("schemes done")
+    if not args.no_parity:
+        out["plummer4096"] = plummer4096(lib, torch)
+        progress("N = 4096 Plummer sphere done")
     if not args.no_hybrid:
         out["hybrid"] = hybrid(lib, torch, m, r, v, tau, args.steps, args.warmup)
         progress("hybrid done")
