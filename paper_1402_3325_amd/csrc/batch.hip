@@ -43,8 +43,9 @@ struct WorkItem {
 
 // MODE selects the starter as in the tile kernel (0 plain, 1 domain
 // statistics, 2 the network's starter, 3 harvest rows); WAVES (1, 2 or 4)
-// wavefronts share each item's sub-steps; DEFKP (MODE 0) calls the solve
-// with the default parameters built in.
+// wavefronts share each item's sub-steps; DEFKP (MODE 0) calls the copy of
+// the solve with the default parameters built in that forms the whole pair
+// map (kepler_map_halves: the batched step splits its drifts into halves).
 template <int MODE, int WAVES, bool DEFKP = false>
 __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1))) void k_batch(int nitems,
                                                         const WorkItem *__restrict__ items,
@@ -141,12 +142,24 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                 const bool collide = act && !(r0sq > 0.0);
                 const bool live = act && !collide;
                 kep::PairFlow f;
-                if constexpr (MODE == 0) {
-                    const kep::PairCoef c =
-                        DEFKP ? kep::kepler_flow_default(live ? tau : 0.0, G * msum, x0, x1, x2,
-                                                         w0, w1, w2, live ? r0sq : 1.0)
-                              : kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
-                                                 w2, live ? r0sq : 1.0, kp);
+                double d[6];
+                if constexpr (MODE == 0 && DEFKP) {
+                    // the whole pair map in the solver's copy (the step's drifts
+                    // split into halves, h = tau/2): nothing kept across the call
+                    const kep::PairMap pm = kep::kepler_map_halves(
+                        live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0);
+                    d[0] = pm.dx0;
+                    d[1] = pm.dx1;
+                    d[2] = pm.dx2;
+                    d[3] = pm.dv0;
+                    d[4] = pm.dv1;
+                    d[5] = pm.dv2;
+                    f.iters = (int)(pm.info >> 16);
+                    f.converged = !(pm.info & 1u);
+                    f.safeguarded = (pm.info & 0x100u) != 0;
+                } else if constexpr (MODE == 0) {
+                    const kep::PairCoef c = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1,
+                                                             x2, w0, w1, w2, live ? r0sq : 1.0, kp);
                     f.fm1 = c.fm1;
                     f.gmt = c.gmt;
                     f.fdot = c.fdot;
@@ -172,11 +185,16 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                     n_learned += (live && gp.used) ? 1u : 0u;
                     n_restart += (live && f.restarted) ? 1u : 0u;
                 }
-                const double a = fma(-h, f.fdot, f.fm1);
-                const double b = fma(-h, f.gdm1, f.gmt);
-                const double d[6] = {fma(a, x0, b * w0), fma(a, x1, b * w1), fma(a, x2, b * w2),
-                                     fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
-                                     fma(f.fdot, x2, f.gdm1 * w2)};
+                if constexpr (!(MODE == 0 && DEFKP)) {
+                    const double a = fma(-h, f.fdot, f.fm1);
+                    const double b = fma(-h, f.gdm1, f.gmt);
+                    d[0] = fma(a, x0, b * w0);
+                    d[1] = fma(a, x1, b * w1);
+                    d[2] = fma(a, x2, b * w2);
+                    d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+                    d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+                    d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+                }
                 // m_j / (m_i + m_j) and m_i / (m_i + m_j) times the flow's 1/mu;
                 // lanes without a pair have zero coefficients (they solve tau = 0)
                 const double wgt_i = G * mj, wgt_j = G * mi;
