@@ -209,6 +209,10 @@ __device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, 
 // s0 + w + SPLIT, ... with j-side slots of its own; at the end the
 // wavefronts' i-side and j-side sums are added in wavefront order.  For small
 // N, where the tiles alone would leave most of the SIMDs' wave slots empty.
+template <bool B> struct BoolTag {
+    static constexpr bool value = B;
+};
+
 template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false, int SPLIT = 1>
 __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np, double tau,
                                                 double cb, double ca, double G,
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     const double *V = S + 4 * (size_t)np;
     const double *XH = S + 7 * (size_t)np;
 
-    __shared__ double sj[7][TILE];          // x y z vx vy vz m of block J (read only)
+    __shared__ double sj[7][TILE];          // x y z vx vy vz G m of block J (read only)
     __shared__ double sjs[SPLIT][6][TILE];  // j-side sums, by wavefront and slot of block J
     __shared__ double sacc[SPLIT > 1 ? SPLIT - 1 : 1][6][TILE]; // i-side sums of wavefronts 1..
     __shared__ unsigned shist[HIST ? 32 : 1];
@@ -254,18 +258,21 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         sj[3][lane] = V[jg];
         sj[4][lane] = V[np + jg];
         sj[5][lane] = V[2 * (size_t)np + jg];
-        sj[6][lane] = M[jg];
+        sj[6][lane] = G * M[jg];
     }
-    // particle i and its sums stay in registers
+    // particle i and its sums stay in registers.  The masses are held as G m:
+    // mu = G m_i + G m_j (G (m_i + m_j) up to its rounding, equal for G = 1)
+    // and the weights G m_j, G m_i of the increments per unit mu are read as
+    // they are.
     const double xi[7] = {XH[ig], XH[np + ig], XH[2 * (size_t)np + ig], V[ig], V[np + ig],
-                          V[2 * (size_t)np + ig], M[ig]};
+                          V[2 * (size_t)np + ig], G * M[ig]};
     double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < 6; ++c) sjs[wv][c][lane] = 0.0;
     if (HIST && wv == 0 && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
-    const double wgt_j = G * xi[6];
+    const double wgt_j = xi[6];
     const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
     const double t2 = tau * tau, mtau = -tau; // MODE 5
     const int nj = n - J * TILE; // valid j slots in this block
@@ -275,46 +282,58 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     // tau = 0: one evaluation, converged, never safeguarded), so the outcomes
     // are summed over all lanes and the trivial ones taken off at the end.
     unsigned info_sum = 0, info_max = 0; // per lane: sum and maximum of kep::pack_info
-    unsigned long long n_solve = 0;      // per wave: pairs solved (ballot counts, or with
-                                         // HALVES the per-lane tallies summed at the end)
+    unsigned long long n_solve = 0;      // per wave: pairs solved (ballot counts)
     unsigned long long n_kick = 0;       // per wave, MODE 5
     GuessCount gc;                       // per wave
     unsigned dom_it = 0;                 // per lane
     int room = kep::DEFER_CAP;           // MODE 4: list slots left
     unsigned long long coll_bits = 0;    // per wave: lanes that met a zero separation
-    unsigned n_live = 0;                 // HALVES: per lane, pairs solved
     bool coll_lane = false;              // HALVES: per lane, a zero separation met
     float rmax = 0.0f;                   // per lane, HIST: largest relative Kepler residual
     __syncthreads();
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
-    for (int s = s0 + wv; s < s1; s += SPLIT) {
+    // The sub-step loop in two copies: FULL for tiles whose 64 i and 64 j
+    // slots all hold particles (every tile but those of the last block), which
+    // need no test of the slots.
+    const bool full_tile = (I + 1) * TILE <= n && (J + 1) * TILE <= n;
+    auto sweep = [&](auto full_tag) __attribute__((always_inline)) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    int p8 = lane8 + 8 * (s0 + wv); // lane8 + 8 s, stepped with s
+    for (int s = s0 + wv; s < s1; s += SPLIT, p8 += 8 * SPLIT) {
         // q scaled by 8 (the byte offset of slot q in a row of doubles) is
-        // formed and tested directly: one vector operation less than q itself
-        const int q8 = (lane8 + 8 * s) & (8 * (TILE - 1));
+        // formed and tested directly: one vector operation less than q itself.
+        // p8 is kept opaque, so that q8 stays one mask of it (left to itself
+        // the compiler forms ((lane + s) & 63) << 3 where q8 is not tested).
+        asm volatile("" : "+v"(p8));
+        const int q8 = p8 & (8 * (TILE - 1));
         const int q = q8 >> 3;
+        // slot q of a row of block J and of this wavefront's j-side sums, by
+        // its byte offset (indexing by q has the compiler form q, then q8 again)
+#define SJ(c) (*(const double *)((const char *)sj[c] + q8))
+#define SJS(c) (*(double *)((char *)sjs[wv][c] + q8))
         // In harvest mode the particle data are read from LDS at every use and
         // the relative state is formed again after the solve (compiler-only
         // fences): its inlined policy's extra live state would otherwise push
         // the loop past 128 VGPRs.  The other modes keep it.
         if (MODE == 3) asm volatile("" ::: "memory");
-        const double mi = xi[6], mj = sj[6][q];
-        const double msum = mi + mj;
-        const bool act = valid_i && (q8 < nj8) && (msum > 0.0) &&
+        const double gmj = SJ(6);
+        const double mu = xi[6] + gmj;
+        const bool act = (FULL || (valid_i && (q8 < nj8))) && (mu > 0.0) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         if constexpr (MODE == 5) {
-            const double X0 = xi[0] - sj[0][q], X1 = xi[1] - sj[1][q], X2 = xi[2] - sj[2][q];
-            const double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q], w2 = xi[5] - sj[5][q];
+            const double X0 = xi[0] - SJ(0), X1 = xi[1] - SJ(1), X2 = xi[2] - SJ(2);
+            const double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4), w2 = xi[5] - SJ(5);
             const double r2 = fma(X0, X0, fma(X1, X1, X2 * X2));
             const double ws = fma(w0, w0, fma(w1, w1, w2 * w2));
-            const bool close = act & hybrid_close(t2, G * msum, r2, ws, e2, e4);
+            const bool close = act & hybrid_close(t2, mu, r2, ws, e2, e4);
             // eq. (28): the relative velocity changes by tau a_ij at X and the
             // position increment vanishes; per unit mu, dv = -tau X / r^3
             const bool kick = act & !close & (r2 > 0.0);
             bool collide = act & !close & !(r2 > 0.0);
             const double rinv = kep::rsqrt_refined(r2); // used only where kick holds
             const double kf = kick ? mtau * (rinv * rinv * rinv) : 0.0;
-            const double wgt_i = G * mj;
+            const double wgt_i = gmj;
             if (!__builtin_amdgcn_ballot_w64(close)) {
                 // no close pair in this sub-step: velocity sums only, weights
                 // folded into the kick
@@ -322,9 +341,9 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
                 ai[3] = fma(ki, X0, ai[3]);
                 ai[4] = fma(ki, X1, ai[4]);
                 ai[5] = fma(ki, X2, ai[5]);
-                sjs[wv][3][q] = fma(kj, X0, sjs[wv][3][q]);
-                sjs[wv][4][q] = fma(kj, X1, sjs[wv][4][q]);
-                sjs[wv][5][q] = fma(kj, X2, sjs[wv][5][q]);
+                SJS(3) = fma(kj, X0, SJS(3));
+                SJS(4) = fma(kj, X1, SJS(4));
+                SJS(5) = fma(kj, X2, SJS(5));
             } else {
                 // the Kepler map of eq. (26), as in MODE 0, for the close lanes
                 double d[6] = {0.0, 0.0, 0.0, kf * X0, kf * X1, kf * X2};
@@ -333,7 +352,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
                 const bool kl = close && (r0sq > 0.0);
                 collide = collide || (close && !(r0sq > 0.0));
                 const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
-                    kl ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, kl ? r0sq : 1.0, kp);
+                    kl ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, kl ? r0sq : 1.0, kp);
                 if (HIST && kl) rmax = fmaxf(rmax, (float)f.resid);
                 if (kl) {
                     const double a = fma(-ca, f.fdot, f.fm1);
@@ -353,7 +372,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     ai[c] = fma(wgt_i, d[c], ai[c]);
-                    sjs[wv][c][q] = fma(-wgt_j, d[c], sjs[wv][c][q]);
+                    SJS(c) = fma(-wgt_j, d[c], SJS(c));
                 }
             }
             n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
@@ -361,11 +380,11 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
             continue;
         }
         // relative state and the pair back-drift of eq. (17) by cb
-        double w0 = xi[3] - sj[3][q], w1 = xi[4] - sj[4][q],
-               w2 = xi[5] - sj[5][q];
-        double x0 = fma(-cb, w0, xi[0] - sj[0][q]);
-        double x1 = fma(-cb, w1, xi[1] - sj[1][q]);
-        double x2 = fma(-cb, w2, xi[2] - sj[2][q]);
+        double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4),
+               w2 = xi[5] - SJ(5);
+        double x0 = fma(-cb, w0, xi[0] - SJ(0));
+        double x1 = fma(-cb, w1, xi[1] - SJ(1));
+        double x2 = fma(-cb, w2, xi[2] - SJ(2));
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
         const bool collide = act && !(r0sq > 0.0);
         bool live = act && !collide;
@@ -377,7 +396,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
             // Pairs that may lie in the network's domain (a necessary condition
             // from the unreduced tau) are listed for k_deferred while the tile's
             // list has room, and skipped here; the rest take the plain solve.
-            const bool cand = live & kep::pair_may_qualify_q(q4, G * msum, r0sq);
+            const bool cand = live & kep::pair_may_qualify_q(q4, mu, r0sq);
             const unsigned long long mask = __builtin_amdgcn_ballot_w64(cand);
             if (mask) {
                 const unsigned long long below =
@@ -392,12 +411,21 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
             }
         }
         if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
-            // per-lane tallies (a ballot of these lane predicates costs two
-            // vector instructions each per sub-step; these cost at most one)
-            n_live += live ? 1u : 0u;
+            // The pairs solved are counted by a ballot of the time passed on
+            // (tau where a pair is solved, 0 elsewhere; tau != 0 is a condition
+            // of this path): the compiler forms a ballot of the combined lane
+            // predicate through two vector operations, of the comparison
+            // through one.  The collisions are tallied per lane.
+            double tsel = live ? tau : 0.0;
+            asm volatile("" : "+v"(tsel)); // keeps the comparison on tsel
+            n_solve += __popcll(__builtin_amdgcn_ballot_w64(tsel != 0.0));
             coll_lane = coll_lane | collide;
-            const kep::PairMap pm = kep::kepler_map_halves(live ? tau : 0.0, G * msum, x0, x1,
-                                                           x2, w0, w1, w2, live ? r0sq : 1.0);
+            // Lanes without a pair pass their own r0^2 with tau = 0, which the
+            // solve takes at s = 0 to zero increments for any finite positive
+            // r0^2; the floor keeps r0^2 = 0 (a collision, or a pair of
+            // coincident massless particles) finite in the solve.
+            const kep::PairMap pm = kep::kepler_map_halves(tsel, mu, x0, x1, x2, w0, w1, w2,
+                                                           fmax(r0sq, 0x1p-1022));
             d[0] = pm.dx0;
             d[1] = pm.dx1;
             d[2] = pm.dx2;
@@ -407,7 +435,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
             info = pm.info;
         } else if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
             const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
-                live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
+                live ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
             if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
             const double a = fma(-ca, f.fdot, f.fm1);
             const double b = fma(-ca, f.gdm1, f.gmt);
@@ -421,7 +449,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         } else {
             kep::PairFlow f;
             if constexpr (MODE == 1) {
-                f = kep::kepler_flow_domain<HIST>(live ? tau : 0.0, G * msum, x0, x1, x2,
+                f = kep::kepler_flow_domain<HIST>(live ? tau : 0.0, mu, x0, x1, x2,
                                                   w0, w1, w2, live ? r0sq : 1.0, kp,
                                                   net.tau2_lo, net.tau2_hi, net.b_lo,
                                                   net.e2_hi);
@@ -431,7 +459,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
                 dom_it += dom ? (unsigned)f.iters : 0u;
             } else { // harvest
                 kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
-                f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1,
+                f = kep::kepler_flow(live ? tau : 0.0, mu, x0, x1, x2, w0, w1,
                                      w2, live ? r0sq : 1.0, kp, gp);
                 const bool dom = live && gp.in_dom;
                 gc.dom += __popcll(__ballot(dom));
@@ -439,12 +467,12 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
             }
             if (MODE == 3) { // the same relative state again, bitwise
                 asm volatile("" ::: "memory");
-                w0 = xi[3] - sj[3][q];
-                w1 = xi[4] - sj[4][q];
-                w2 = xi[5] - sj[5][q];
-                x0 = fma(-cb, w0, xi[0] - sj[0][q]);
-                x1 = fma(-cb, w1, xi[1] - sj[1][q]);
-                x2 = fma(-cb, w2, xi[2] - sj[2][q]);
+                w0 = xi[3] - SJ(3);
+                w1 = xi[4] - SJ(4);
+                w2 = xi[5] - SJ(5);
+                x0 = fma(-cb, w0, xi[0] - SJ(0));
+                x1 = fma(-cb, w1, xi[1] - SJ(1));
+                x2 = fma(-cb, w2, xi[2] - SJ(2));
             }
             const double a = fma(-ca, f.fdot, f.fm1);
             const double b = fma(-ca, f.gdm1, f.gmt);
@@ -459,11 +487,11 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j),
         // times mu = G (m_i + m_j) that the increments are divided by; lanes
         // without a pair have zero increments (they solve tau = 0)
-        const double wgt_i = G * mj;
+        const double wgt_i = gmj;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             ai[c] = fma(wgt_i, d[c], ai[c]);
-            sjs[wv][c][q] = fma(-wgt_j, d[c], sjs[wv][c][q]);
+            SJS(c) = fma(-wgt_j, d[c], SJS(c));
         }
         info_sum += info;
         info_max = max(info_max, info);
@@ -473,11 +501,14 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         }
         if (HIST && live) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
     }
+    };
+    if (full_tile) sweep(BoolTag<true>{});
+    else sweep(BoolTag<false>{});
+#undef SJ
+#undef SJS
 
-    if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
-        n_solve = wave_sum(n_live);
+    if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4))
         coll_bits = __builtin_amdgcn_ballot_w64(coll_lane);
-    }
     if constexpr (SPLIT > 1) {
         if (wv > 0)
             for (int c = 0; c < 6; ++c) sacc[wv - 1][c][lane] = ai[c];
@@ -577,15 +608,14 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
             j = p.y;
         }
         // the relative state exactly as k_pairs forms it
-        const double mi = M[i], mj = M[j];
-        const double msum = mi + mj;
+        const double gmi = G * M[i], gmj = G * M[j];
         const double w0 = V[i] - V[j], w1 = V[np + i] - V[np + j],
                      w2 = V[2 * (size_t)np + i] - V[2 * (size_t)np + j];
         const double x0 = fma(-cb, w0, XH[i] - XH[j]);
         const double x1 = fma(-cb, w1, XH[np + i] - XH[np + j]);
         const double x2 = fma(-cb, w2, XH[2 * (size_t)np + i] - XH[2 * (size_t)np + j]);
         const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
-        const double mu = has ? G * msum : 0.0;
+        const double mu = has ? gmi + gmj : 0.0;
         const double s_net = kep::net_starter(net, tau, mu, x0, x1, x2, w0, w1, w2, r0sq);
         kep::NetGuess<2> gp(net, i, j, s_net);
         const kep::PairFlow f = kep::kepler_flow(has ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2,
@@ -596,7 +626,7 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
                              fma(f.fdot, x0, f.gdm1 * w0), fma(f.fdot, x1, f.gdm1 * w1),
                              fma(f.fdot, x2, f.gdm1 * w2)};
         // the weights of k_pairs (the flow's coefficients are per unit mu)
-        const double wgt_i = G * mj, wgt_j = G * mi;
+        const double wgt_i = gmj, wgt_j = gmi;
         __syncthreads(); // the previous item's readers of sc are done
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -886,9 +916,10 @@ void launch_pairs_h(int mode, int split, int ntiles, hipStream_t st, int n, int 
 {
     // the plain solve with the default parameters built in, where they apply,
     // and with the increments formed in the solver's copy where the drifts
-    // split into halves
+    // split into halves of a step that is not zero (that kernel counts the
+    // pairs it solves from the time it passes to the solver)
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
-    const bool halves = !HIST && defkp && cb == ca && ca == 0.5 * dt;
+    const bool halves = !HIST && defkp && cb == ca && ca == 0.5 * dt && dt != 0.0;
 #define SAKURA_TILE_ARGS split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, \
                          kp, step, net
     switch (mode) {
