@@ -277,15 +277,35 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
     const double s = st.s;
     const KepEval e = kepler_eval<TIER>(s, beta, eta, zeta, r0, t);
     double ds;
-    bool nt = false;
     if (TIER == 2 && newton) {
         const double dn = e.F * rcp_step(e.r);
         if (SAKURA_WAVE_ALL(fabs(dn) <= 0x1p-23 * fabs(s - dn))) {
-            ds = dn;
-            nt = true;
-        } else {
-            ds = laguerre_step<true>(e);
+            // every lane takes the root s - dn (the shift of the general
+            // path below, with done on every lane: to first order where it
+            // suffices on every lane, else to second)
+            const double sn = s - dn, d = -dn;
+            double G3 = fma(d, e.G2, e.G3);
+            double G2 = fma(d, e.G1, e.G2);
+            double G1 = fma(d, e.G0, e.G1);
+            if (!SAKURA_WAVE_ALL(0x1p28 * fabs(dn) <= fabs(sn))) {
+                // (a branch, not both orders formed and one selected: the
+                // empty statement cannot be executed speculatively)
+                asm volatile("");
+                const double d2 = 0.5 * d * d;
+                G3 = fma(d2, e.G1, G3);
+                G2 = fma(d2, e.G0, G2);
+                G1 = fma(d2, -beta * e.G1, G1);
+            }
+            st.G1 = G1;
+            st.G2 = G2;
+            st.G3 = G3;
+            st.r = fma(eta, G1, fma(zeta, G2, r0));
+            st.s = sn;
+            st.F_prev = e.F;
+            st.ds_prev = dn;
+            return 2;
         }
+        ds = laguerre_step<true>(e);
     } else {
         ds = laguerre_step<TIER == 2>(e);
     }
@@ -293,9 +313,7 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
     const double sn = s - ds;
     const double asn = fabs(sn);
     bool done;
-    if (TIER == 2 && nt)
-        done = true;
-    else if (TIER == 2 && easy)
+    if (TIER == 2 && easy)
         done = ads <= tol * fabs(s) || e.F == 0.0 || ads <= 0x1p-16 * asn;
     else
         done = ads <= tol * fabs(s) || e.F == 0.0 ||
@@ -305,20 +323,12 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
     double G2 = fma(d, e.G1, e.G2);
     double G1 = fma(d, e.G0, e.G1);
     // order of the shift that suffices on every lane that takes the root: the
-    // first, else the second, else the third.  After a Newton step on every
-    // lane (|ds| <= 2^-23 |s - ds|, all lanes done) the second always does,
-    // and the test for the first is a plain comparison on every lane.
+    // first, else the second, else the third (after a Newton step on every
+    // lane, above, |ds| <= 2^-23 |s - ds| and the second always does)
     bool first = false, second = false;
     if (TIER == 2) {
-        if (nt) {
-            // (scaled on the other side than below: the two comparisons stay
-            // apart, each next to its ballot)
-            first = SAKURA_WAVE_ALL(0x1p28 * ads <= asn);
-            second = true;
-        } else {
-            first = SAKURA_WAVE_ALL(!done || ads <= 0x1p-28 * asn);
-            second = first || SAKURA_WAVE_ALL(!done || ads <= 0x1p-18 * asn);
-        }
+        first = SAKURA_WAVE_ALL(!done || ads <= 0x1p-28 * asn);
+        second = first || SAKURA_WAVE_ALL(!done || ads <= 0x1p-18 * asn);
     }
     if (!first) {
         const double d2 = 0.5 * d * d;
@@ -430,9 +440,14 @@ SAKURA_HD inline double reduce_time(double tau, double mu, double beta, double &
 // t ~ exp(k|s|) (r0 k^2 + eta k sgn t + mu) / (2 k^3), k = sqrt(-beta).
 // A starter beyond |s| <= s_half or of the wrong sign is replaced by u,
 // clamped to that bound.
+SAKURA_HD inline double starter_bounded(double s, double u, double s_half)
+{
+    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = fmin(fmax(u, -s_half), s_half);
+    return s;
+}
 SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0inv, double eta,
                                       double zeta, double beta, double mu, double s_half,
-                                      double &csum_out)
+                                      double &csum_out, bool &all_small)
 {
     const double p = eta * r0inv;                 // 2 A2
     const double A3 = (1.0 / 6.0) * (zeta * r0inv);
@@ -442,6 +457,14 @@ SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0in
     const double csum = fabs(corr1) + fabs(corr2);
     csum_out = csum;
     double corr = corr1 + corr2;
+    all_small = SAKURA_WAVE_ALL(csum <= 0x1p-9);
+    if (all_small) {
+        // third order on every lane of the wavefront: s = u (1 + corr) with
+        // |corr| <= 2^-9 has the sign of u (or is zero with it), so of the
+        // replacement's conditions only the bound can hold
+        const double s = fma(u, corr, u);
+        return SAKURA_WAVE_ALL(fabs(s) <= s_half) ? s : starter_bounded(s, u, s_half);
+    }
     if (csum > 0x1p-9) {
         const double A2 = 0.5 * p;
         const double A4 = (-1.0 / 24.0) * beta * eta * r0inv;
@@ -461,8 +484,7 @@ SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0in
             s = copysign(log1p(2.0 * k * k * k * fabs(t) / D) / k, t);
         }
     }
-    if (!(fabs(s) <= s_half) || (s > 0.0) != (u > 0.0)) s = fmin(fmax(u, -s_half), s_half);
-    return s;
+    return starter_bounded(s, u, s_half);
 }
 
 // Bracket of the root: it has the sign of t since t(0) = 0 and t(s)
@@ -557,7 +579,8 @@ SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau,
     const double t = reduce_time(tau, mu, beta, s_half, tshift_mu);
     const double u = t * r0inv;
     double csum;
-    double s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum);
+    bool all_small; // csum <= 2^-9 on every lane
+    double s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum, all_small);
     bool replaced = false;
     if (Guess::active) {
         double lo, hi;
@@ -576,7 +599,8 @@ SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau,
     }
 
     // the simplified acceptance of kepler_first (uniform over the wavefront)
-    const bool easy = kp.tol >= 0x1p-52 && SAKURA_WAVE_ALL(csum <= 0x1p-9 && !replaced);
+    const bool easy =
+        kp.tol >= 0x1p-52 && all_small && (!Guess::active || SAKURA_WAVE_ALL(!replaced));
     KepIter st{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
     int it = 0;
     int res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, easy, it,
@@ -584,7 +608,7 @@ SAKURA_HD __attribute__((always_inline)) inline PairFlow kepler_flow(double tau,
     bool restarted = false;
     if (Guess::active && res == 0 && replaced) {
         restarted = true;
-        s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum);
+        s = plain_starter(t, u, r0, r0inv, eta, zeta, beta, mu, s_half, csum, all_small);
         st = KepIter{s, 0.0, 0.0, 1e300, 1e300, 0.0, 0.0, 0.0, r0, false};
         int it2 = 0;
         res = kepler_search(st, beta, eta, zeta, r0, t, u, s_half, kp, false, it2);
