@@ -35,10 +35,10 @@ FLOPS_SETUP = 160
 FLOPS_PER_ITER = 70
 # The same work counted in the kernel source along the path almost every pair
 # takes (one evaluation in the cheapest tier, accepted by its error bound):
-# pair set-up and back-drift 19, Kepler set-up, starter and tier choice 42, the
-# evaluation with its Halley step, tests and shift 57, Lagrange coefficients
-# 12, increments, weights and the two-sided sums 47; 92 per further evaluation.
-KERNEL_FLOPS_FIRST = 19 + 42 + 57 + 12 + 47
+# pair set-up and back-drift 18, Kepler set-up, starter and tier choice 42, the
+# evaluation with its Newton or Halley step, tests and shift 57, Lagrange coefficients
+# 12, increments, weights and the two-sided sums 46; 92 per further evaluation.
+KERNEL_FLOPS_FIRST = 18 + 42 + 57 + 12 + 46
 KERNEL_FLOPS_PER_EXTRA_ITER = 92
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
