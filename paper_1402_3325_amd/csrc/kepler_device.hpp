@@ -121,9 +121,16 @@ SAKURA_HD inline double fma_sc(double a, double b, double c)
     asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
     return r;
 }
+SAKURA_HD inline double fma_v(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 #else
 inline double add_sc(double z, double c) { return z + c; }
 inline double fma_sc(double a, double b, double c) { return fma(a, b, c); }
+inline double fma_v(double a, double b, double c) { return fma(a, b, c); }
 #endif
 
 // The same functions for |z| <= 2^-10 only: four terms each leave a truncation
@@ -720,17 +727,17 @@ SAKURA_HD __attribute__((noinline)) PairMap kepler_map_halves(double tau, double
     constexpr KeplerParams kp{DEFAULT_TOL, DEFAULT_MAX_ITER};
     NoGuess g;
     const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
+    PairMap m;
+    m.info = ((unsigned)f.iters << 16) | (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u);
     const double ca = 0.5 * tau;
     const double a = fma(-ca, f.fdot, f.fm1);
     const double b = fma(-ca, f.gdm1, f.gmt);
-    PairMap m;
     m.dx0 = fma(a, x0, b * w0);
     m.dv0 = fma(f.fdot, x0, f.gdm1 * w0);
     m.dx1 = fma(a, x1, b * w1);
-    m.dv1 = fma(f.fdot, x1, f.gdm1 * w1);
-    m.dx2 = fma(a, x2, b * w2);
+    m.dv1 = fma_v(f.fdot, x1, f.gdm1 * w1);
     m.dv2 = fma(f.fdot, x2, f.gdm1 * w2);
-    m.info = ((unsigned)f.iters << 16) | (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u);
+    m.dx2 = fma_v(a, x2, b * w2);
     return m;
 }
 
