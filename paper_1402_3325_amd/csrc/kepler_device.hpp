@@ -121,6 +121,12 @@ SAKURA_HD inline double fma_sc(double a, double b, double c)
     asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
     return r;
 }
+SAKURA_HD inline double vmov_sc(double c)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "s"(c));
+    return r;
+}
 SAKURA_HD inline double fma_v(double a, double b, double c)
 {
     double r;
@@ -131,6 +137,7 @@ SAKURA_HD inline double fma_v(double a, double b, double c)
 inline double add_sc(double z, double c) { return z + c; }
 inline double fma_sc(double a, double b, double c) { return fma(a, b, c); }
 inline double fma_v(double a, double b, double c) { return fma(a, b, c); }
+inline double vmov_sc(double c) { return c; }
 #endif
 
 // The same functions for |z| <= 2^-10 only: four terms each leave a truncation
@@ -308,8 +315,6 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
             st.G3 = G3;
             st.r = fma(eta, G1, fma(zeta, G2, r0));
             st.s = sn;
-            st.F_prev = e.F;
-            st.ds_prev = dn;
             return 2;
         }
         ds = laguerre_step<true>(e);
@@ -418,7 +423,7 @@ SAKURA_HD inline double reduce_time(double tau, double mu, double beta, double &
                                     double &tshift_mu)
 {
     double t = tau;
-    s_half = 1e300;
+    s_half = vmov_sc(1e300); // one vector move from a scalar pair, where a literal takes two
     tshift_mu = 0.0;
     if (beta > 0.0) {
         const double ib = rsqrt_refined(beta);
@@ -534,7 +539,7 @@ SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double 
                                    double t, double u, double s_half, const KeplerParams &kp,
                                    bool easy, int &it, bool newton = false)
 {
-    const double z0 = fabs(beta * st.s * st.s);
+    const double z0 = fabs(beta * (st.s * st.s)); // z as the evaluation forms it
     int res;
     if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
         res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol, easy, newton);
@@ -726,12 +731,15 @@ SAKURA_HD __attribute__((noinline)) PairMap kepler_map_halves(double tau, double
 {
     constexpr KeplerParams kp{DEFAULT_TOL, DEFAULT_MAX_ITER};
     NoGuess g;
+    // -ca = -tau/2 formed first (kept there by the empty statement): tau then
+    // ends where the flow takes it, and the flow's time can take its register
+    double mca = -0.5 * tau;
+    asm volatile("" : "+v"(mca));
     const PairFlow f = kepler_flow(tau, mu, x0, x1, x2, w0, w1, w2, r0sq, kp, g);
     PairMap m;
     m.info = ((unsigned)f.iters << 16) | (f.safeguarded ? 0x100u : 0u) | (f.converged ? 0u : 1u);
-    const double ca = 0.5 * tau;
-    const double a = fma(-ca, f.fdot, f.fm1);
-    const double b = fma(-ca, f.gdm1, f.gmt);
+    const double a = fma(mca, f.fdot, f.fm1);
+    const double b = fma(mca, f.gdm1, f.gmt);
     m.dx0 = fma(a, x0, b * w0);
     m.dv0 = fma(f.fdot, x0, f.gdm1 * w0);
     m.dx1 = fma(a, x1, b * w1);

@@ -294,9 +294,11 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
 
     const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
     // The sub-step loop in two copies: FULL for tiles whose 64 i and 64 j
-    // slots all hold particles (every tile but those of the last block), which
-    // need no test of the slots.
-    const bool full_tile = (I + 1) * TILE <= n && (J + 1) * TILE <= n;
+    // slots all hold particles of positive mass (every tile but those of the
+    // last block, in a system without massless particles), which need no test
+    // of the slots or of mu > 0.
+    const bool full_tile = (I + 1) * TILE <= n && (J + 1) * TILE <= n &&
+                           __all(xi[6] > 0.0 && sj[6][lane] > 0.0);
     auto sweep = [&](auto full_tag) __attribute__((always_inline)) {
     constexpr bool FULL = decltype(full_tag)::value;
     int p8 = lane8 + 8 * (s0 + wv); // lane8 + 8 s, stepped with s
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         if (MODE == 3) asm volatile("" ::: "memory");
         const double gmj = SJ(6);
         const double mu = xi[6] + gmj;
-        const bool act = (FULL || (valid_i && (q8 < nj8))) && (mu > 0.0) &&
+        const bool act = (FULL || (valid_i && (q8 < nj8) && (mu > 0.0))) &&
                          !(diag && s == TILE / 2 && lane >= TILE / 2);
         if constexpr (MODE == 5) {
             const double X0 = xi[0] - SJ(0), X1 = xi[1] - SJ(1), X2 = xi[2] - SJ(2);
