@@ -179,8 +179,14 @@ struct KepIter {
 // for: 0 nothing; 1 |z| <= 2^-10 (four-term series); 2 |z| <= 2^-14, where
 // three terms of each series leave a truncation below 2^-56.
 struct KepEval {
-    double G0, G1, G2, G3, F, r, Fpp;
+    double G0, G1, G2, G3, F, r;
 };
+// F'' = t''(s) = eta G0 + zeta G1, formed where a step or test needs it (the
+// Newton step of the common path does not)
+SAKURA_HD inline double kepler_fpp(const KepEval &e, double eta, double zeta)
+{
+    return fma(eta, e.G0, zeta * e.G1);
+}
 template <int TIER>
 SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double zeta, double r0,
                                      double t)
@@ -206,7 +212,6 @@ SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double z
     e.G0 = fma(-z, c2, 1.0);
     e.F = fma(r0, s, fma(eta, e.G2, fma(zeta, e.G3, -t)));
     e.r = fma(eta, e.G1, fma(zeta, e.G2, r0));
-    e.Fpp = fma(eta, e.G0, zeta * e.G1);
     return e;
 }
 
@@ -215,9 +220,9 @@ SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double z
 // |F F''| <= 2^-22 r^2: the two agree to a relative q^2/10, q = 5 F F'' / 4 r^2,
 // i.e. below 2^-42.
 template <bool HALLEY>
-SAKURA_HD inline double laguerre_step(const KepEval &e)
+SAKURA_HD inline double laguerre_step(const KepEval &e, double eta, double zeta)
 {
-    const double FFpp = e.F * e.Fpp;
+    const double FFpp = e.F * kepler_fpp(e, eta, zeta);
     if (HALLEY && fabs(FFpp) <= 0x1p-22 * (e.r * e.r))
         return e.F * e.r * rcp_step(fma(-0.5, FFpp, e.r * e.r));
     const double disc = fma(16.0 * e.r, e.r, -20.0 * FFpp);
@@ -236,7 +241,7 @@ SAKURA_HD inline bool step_accepted(const KepEval &e, double ds, double sn, doub
                                     double eta, double zeta, double tol)
 {
     const double ads = fabs(ds), asn = fabs(sn);
-    const double aFpp = fabs(e.Fpp);
+    const double aFpp = fabs(kepler_fpp(e, eta, zeta));
     const double Fppp = fma(zeta, e.G0, -beta * eta * e.G1);
     const double err_r2 = ads * ads * ads * fma(fabs(Fppp), e.r, aFpp * aFpp);
     return ads <= 0x1p-16 * asn && err_r2 <= 0.25 * tol * asn * e.r * e.r;
@@ -317,9 +322,9 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
             st.s = sn;
             return 2;
         }
-        ds = laguerre_step<true>(e);
+        ds = laguerre_step<true>(e, eta, zeta);
     } else {
-        ds = laguerre_step<TIER == 2>(e);
+        ds = laguerre_step<TIER == 2>(e, eta, zeta);
     }
     const double ads = fabs(ds);
     const double sn = s - ds;
@@ -374,7 +379,7 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     const KepEval e = kepler_eval<0>(s, beta, eta, zeta, r0, t);
     if (e.F < 0.0) st.lo = s;
     else st.hi = s;
-    const double ds = laguerre_step<false>(e);
+    const double ds = laguerre_step<false>(e, eta, zeta);
     const double ads = fabs(ds), as = fabs(s);
     // Converged at s: the correction is below tol |s|, or it sits at the
     // rounding floor of F (tiny and no longer shrinking).
@@ -461,11 +466,12 @@ SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0in
                                       double zeta, double beta, double mu, double s_half,
                                       double &csum_out, bool &all_small)
 {
-    const double p = eta * r0inv;                 // 2 A2
+    const double p = eta * r0inv; // 2 A2
+    const double A2 = 0.5 * p;
     const double A3 = (1.0 / 6.0) * (zeta * r0inv);
-    const double corr1 = -0.5 * (p * u);           // -A2 u
+    const double corr1 = -0.5 * (p * u);          // -A2 u
     const double uu = u * u;
-    const double corr2 = fma(0.5 * p, p, -A3) * uu; // (2 A2^2 - A3) u^2
+    const double corr2 = fma(A2, p, -A3) * uu; // (2 A2^2 - A3) u^2
     const double csum = fabs(corr1) + fabs(corr2);
     csum_out = csum;
     double corr = corr1 + corr2;
@@ -478,7 +484,6 @@ SAKURA_HD inline double plain_starter(double t, double u, double r0, double r0in
         return SAKURA_WAVE_ALL(fabs(s) <= s_half) ? s : starter_bounded(s, u, s_half);
     }
     if (csum > 0x1p-9) {
-        const double A2 = 0.5 * p;
         const double A4 = (-1.0 / 24.0) * beta * eta * r0inv;
         const double A5 = (-1.0 / 120.0) * beta * zeta * r0inv;
         const double A22 = A2 * A2;
