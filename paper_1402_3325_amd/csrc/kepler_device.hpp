@@ -320,6 +320,11 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
             st.G3 = G3;
             st.r = fma(eta, G1, fma(zeta, G2, r0));
             st.s = sn;
+            // (not read after a root is taken; written, the compiler keeps this
+            // path apart from the Halley step's instead of joining the two
+            // with moves of the iteration state's initial values)
+            st.F_prev = e.F;
+            st.ds_prev = dn;
             return 2;
         }
         ds = laguerre_step<true>(e, eta, zeta);
