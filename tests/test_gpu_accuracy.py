@@ -104,7 +104,12 @@ def test_plummer_bh_energy_error_falls_with_mass_ratio(torch, lib, oracle):
         if q >= 1e6:  # regular orbits: the oracle's run is the same run
             ro, vo = oracle.evolve(m, r, v, tau, nsteps)
             de_o = _rel_dE(oracle, m, r, v, ro, vo)
-            assert abs(de[q] - de_o) <= 0.01 * de_o + 1e-15, (q, de[q], de_o)
+            # to 1 % of the energy error, plus the rounding of the two runs: each
+            # carries its own random walk of about sqrt(nsteps) 2^-53 = 3.5e-15
+            # in the relative energy after 1000 steps (the two integrators
+            # round differently), allowed three times over
+            floor = 3.0 * np.sqrt(nsteps) * 2.0 ** -53
+            assert abs(de[q] - de_o) <= 0.01 * de_o + floor, (q, de[q], de_o)
     print({f"{q:.0e}": f"{e:.2e}" for q, e in de.items()})
     assert de[1e3] > de[1e6] > de[1e9] > de[1e12]
     # the error falls about as 1/q once the black hole dominates
