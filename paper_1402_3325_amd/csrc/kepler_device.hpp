@@ -140,12 +140,16 @@ inline double fma_v(double a, double b, double c) { return fma(a, b, c); }
 inline double vmov_sc(double c) { return c; }
 #endif
 
-// The same functions for |z| <= 2^-10 only: four terms each leave a truncation
-// below 1e-18 relative.
+// The same functions for |z| <= 2^-6 only: five terms each leave a truncation
+// below 4e-18 relative (the first term dropped, z^5/12! against 1/2 and
+// z^5/13! against 1/6), without the argument reduction.
 SAKURA_HD inline void stumpff23_small(double z, double &c2, double &c3)
 {
-    c2 = fma(fma(fma(-z, 1.0 / 40320.0, 1.0 / 720.0), -z, 1.0 / 24.0), -z, 0.5);
-    c3 = fma(fma(fma(-z, 1.0 / 362880.0, 1.0 / 5040.0), -z, 1.0 / 120.0), -z, 1.0 / 6.0);
+    c2 = fma(fma(fma(fma(-z, 1.0 / 3628800.0, 1.0 / 40320.0), -z, 1.0 / 720.0), -z, 1.0 / 24.0),
+             -z, 0.5);
+    c3 = fma(fma(fma(fma(-z, 1.0 / 39916800.0, 1.0 / 362880.0), -z, 1.0 / 5040.0), -z,
+                 1.0 / 120.0),
+             -z, 1.0 / 6.0);
 }
 
 #ifndef SAKURA_WAVE_ALL
@@ -176,7 +180,7 @@ struct KepIter {
 
 // The quantities of one evaluation of t(s) - t at s, with c2(z), c3(z) of
 // z = beta s^2 evaluated by the tier every lane of the wavefront qualifies
-// for: 0 nothing; 1 |z| <= 2^-10 (four-term series); 2 |z| <= 2^-14, where
+// for: 0 nothing; 1 |z| <= 2^-6 (five-term series); 2 |z| <= 2^-14, where
 // three terms of each series leave a truncation below 2^-56.
 struct KepEval {
     double G0, G1, G2, G3, F, r;
@@ -215,15 +219,19 @@ SAKURA_HD inline KepEval kepler_eval(double s, double beta, double eta, double z
     return e;
 }
 
-// Laguerre step of order 5 at an evaluation; with HALLEY (every lane has
-// |z| <= 2^-14) it is taken in its Halley form F r / (r^2 - F F''/2) while
-// |F F''| <= 2^-22 r^2: the two agree to a relative q^2/10, q = 5 F F'' / 4 r^2,
-// i.e. below 2^-42.
-template <bool HALLEY>
+// Laguerre step of order 5 at an evaluation, or the Halley step
+// F r / (r^2 - F F''/2) where |F F''| is small against r^2.  HALLEY 1 (every
+// lane has |z| <= 2^-14) takes it while |F F''| <= 2^-22 r^2, where the two
+// agree to a relative q^2/10, q = 5 F F'' / 4 r^2, i.e. below 2^-42.  HALLEY 2
+// (the first evaluation of the other tiers, whose acceptance test bounds the
+// cubic error of either step) takes it while |F F''| <= 2^-8 r^2: near the
+// root, where a step is accepted, q is small anyway (q ~ ds t''/r), and farther
+// out Laguerre's step keeps its wider convergence.  HALLEY 0: Laguerre's.
+template <int HALLEY>
 SAKURA_HD inline double laguerre_step(const KepEval &e, double eta, double zeta)
 {
     const double FFpp = e.F * kepler_fpp(e, eta, zeta);
-    if (HALLEY && fabs(FFpp) <= 0x1p-22 * (e.r * e.r))
+    if (HALLEY != 0 && fabs(FFpp) <= (HALLEY == 1 ? 0x1p-22 : 0x1p-8) * (e.r * e.r))
         return e.F * e.r * rcp_step(fma(-0.5, FFpp, e.r * e.r));
     const double disc = fma(16.0 * e.r, e.r, -20.0 * FFpp);
     return 5.0 * e.F * rcp_step(e.r + sqrt_step(fabs(disc)));
@@ -327,9 +335,9 @@ SAKURA_HD inline int kepler_first(KepIter &st, double beta, double eta, double z
             st.ds_prev = dn;
             return 2;
         }
-        ds = laguerre_step<true>(e, eta, zeta);
+        ds = laguerre_step<1>(e, eta, zeta);
     } else {
-        ds = laguerre_step<TIER == 2>(e, eta, zeta);
+        ds = laguerre_step<TIER == 2 ? 1 : 2>(e, eta, zeta);
     }
     const double ads = fabs(ds);
     const double sn = s - ds;
@@ -384,7 +392,7 @@ SAKURA_HD inline int kepler_iterate(KepIter &st, double beta, double eta, double
     const KepEval e = kepler_eval<0>(s, beta, eta, zeta, r0, t);
     if (e.F < 0.0) st.lo = s;
     else st.hi = s;
-    const double ds = laguerre_step<false>(e, eta, zeta);
+    const double ds = laguerre_step<0>(e, eta, zeta);
     const double ads = fabs(ds), as = fabs(s);
     // Converged at s: the correction is below tol |s|, or it sits at the
     // rounding floor of F (tiny and no longer shrinking).
@@ -553,7 +561,7 @@ SAKURA_HD inline int kepler_search(KepIter &st, double beta, double eta, double 
     int res;
     if (SAKURA_WAVE_ALL(z0 <= 0x1p-14))
         res = kepler_first<2>(st, beta, eta, zeta, r0, t, kp.tol, easy, newton);
-    else if (SAKURA_WAVE_ALL(z0 <= 0x1p-10))
+    else if (SAKURA_WAVE_ALL(z0 <= 0x1p-6))
         res = kepler_first<1>(st, beta, eta, zeta, r0, t, kp.tol, false, false);
     else
         res = kepler_first<0>(st, beta, eta, zeta, r0, t, kp.tol, false, false);
