@@ -61,13 +61,18 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                                                 kep::KeplerParams kp, const kep::GuessNet net,
                                                 unsigned *queue)
 {
-    __shared__ double sj[7][TILE];         // x y z vx vy vz m of every lane this step
+    __shared__ double sj[7][TILE];         // x y z vx vy vz G m of every lane this step
     __shared__ double sa[WAVES][6][TILE];  // j-side sums, per wavefront
     __shared__ double sacc[WAVES][6][TILE]; // i-side sums, exchanged (WAVES 2)
     __shared__ int s_item;
     const int lane = WAVES == 1 ? (int)threadIdx.x : (int)threadIdx.x % TILE;
-    const int wv = WAVES == 1 ? 0 : (int)threadIdx.x / TILE;
-    unsigned n_solve = 0, it_sum = 0, it_max = 0, n_fb = 0;
+    // (wave-uniform, so that the sub-step index and its tests are scalar)
+    const int wv = WAVES == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x / TILE);
+    // Every lane solves a problem in every sub-step (lanes without a pair solve
+    // tau = 0: one evaluation, converged, never safeguarded); their outcomes are
+    // summed per step and the trivial ones taken off at the end.
+    unsigned n_live = 0, it_all = 0, it_max_all = 0, n_fb = 0; // per lane
+    unsigned n_sub = 0;                                          // per wave: sub-steps taken
     unsigned dom_n = 0, dom_it = 0, n_learned = 0, n_restart = 0; // per lane
 
     for (;;) {
@@ -81,6 +86,7 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
             __syncthreads();
             item = s_item;
         }
+        item = __builtin_amdgcn_readfirstlane(item); // the item's fields in scalar registers
         if (item >= nitems) break;
         const WorkItem w = items[item];
         const int L = w.L;
@@ -94,6 +100,16 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
         const double tau = in_group ? dt[sys] : 0.0;
         const double h = 0.5 * tau;
         const int64_t p = off + l;
+        // Byte offset q8 of the partner's slot, (l + s) mod L within the lane's
+        // group, stepped with s (lanes past the last group keep their own slot:
+        // a group of one).  The partner holds a particle while q8 < valid8.
+        const int L8 = 8 * (lane_in_tile ? L : 1);
+        const int base8 = lane_in_tile ? 8 * (g * L) : 8 * lane;
+        const int lim8 = base8 + L8;
+        const int inc8 = lane_in_tile ? 8 * (WAVES % L) : 0;
+        const int q8_first = lane_in_tile ? base8 + 8 * ((l + 1 + wv) % L) : base8;
+        const int valid8 = base8 + 8 * nsys_n;
+        const bool upper = 2 * l >= L; // even L: the middle sub-step is the lower half's
         double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
         if (valid) {
             mi = m[p];
@@ -107,7 +123,9 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
             else if (!(mi >= 0.0)) record_error(cnt, ST_INVAL, 0);
         }
         const int nsub = (L - 1) / 2 + ((L & 1) ? 0 : 1);
-        unsigned flags = 0;
+        // sub-steps this wavefront takes per step: s = 1 + wv, 1 + wv + WAVES, ...
+        const unsigned nsub_w = nsub > wv ? (unsigned)((nsub - 1 - wv) / WAVES + 1) : 0u;
+        const double gmi = G * mi; // the masses as G m (mi is 0 where !valid)
 
         for (long long step = 0; step < nsteps; ++step) {
             double xh[3];
@@ -120,70 +138,71 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                 sj[3][lane] = u[0];
                 sj[4][lane] = u[1];
                 sj[5][lane] = u[2];
-                sj[6][lane] = valid ? mi : 0.0;
+                sj[6][lane] = valid ? gmi : 0.0;
             }
             for (int c = 0; c < 6; ++c) sa[wv][c][lane] = 0.0;
             __syncthreads();
 
             double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            unsigned info_sum = 0, info_max = 0; // per lane, this step: of kep::pack_info
+            bool coll_lane = false;              // per lane, this step: a zero separation met
+            int q8 = q8_first;
             for (int s = 1 + wv; s <= nsub; s += WAVES) {
-                int ql = l + s;
-                ql = ql >= L ? ql - L : ql;
-                const int q = lane_in_tile ? g * L + ql : lane; // always inside [0, 64)
-                const double mj = sj[6][q];
-                const double msum = mi + mj;
-                const bool act = valid && ql < nsys_n && msum > 0.0 &&
-                                 !((L & 1) == 0 && 2 * s == L && 2 * l >= L);
-                const double w0 = u[0] - sj[3][q], w1 = u[1] - sj[4][q], w2 = u[2] - sj[5][q];
-                const double x0 = fma(-h, w0, xh[0] - sj[0][q]);
-                const double x1 = fma(-h, w1, xh[1] - sj[1][q]);
-                const double x2 = fma(-h, w2, xh[2] - sj[2][q]);
+#define SJ(c) (*(const double *)((const char *)sj[c] + q8))
+#define SA(c) (*(double *)((char *)sa[wv][c] + q8))
+                const double gmj = SJ(6);
+                const double mu = gmi + gmj;
+                const bool act = valid && q8 < valid8 && mu > 0.0 &&
+                                 !((L & 1) == 0 && 2 * s == L && upper);
+                const double w0 = u[0] - SJ(3), w1 = u[1] - SJ(4), w2 = u[2] - SJ(5);
+                const double x0 = fma(-h, w0, xh[0] - SJ(0));
+                const double x1 = fma(-h, w1, xh[1] - SJ(1));
+                const double x2 = fma(-h, w2, xh[2] - SJ(2));
                 const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
                 const bool collide = act && !(r0sq > 0.0);
                 const bool live = act && !collide;
                 kep::PairFlow f;
                 double d[6];
+                unsigned info;
                 if constexpr (MODE == 0 && DEFKP) {
                     // the whole pair map in the solver's copy (the step's drifts
                     // split into halves, h = tau/2): nothing kept across the call
                     const kep::PairMap pm = kep::kepler_map_halves(
-                        live ? tau : 0.0, G * msum, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0);
+                        live ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0);
                     d[0] = pm.dx0;
                     d[1] = pm.dx1;
                     d[2] = pm.dx2;
                     d[3] = pm.dv0;
                     d[4] = pm.dv1;
                     d[5] = pm.dv2;
-                    f.iters = (int)(pm.info >> 16);
-                    f.converged = !(pm.info & 1u);
-                    f.safeguarded = (pm.info & 0x100u) != 0;
+                    info = pm.info;
                 } else if constexpr (MODE == 0) {
-                    const kep::PairCoef c = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1,
-                                                             x2, w0, w1, w2, live ? r0sq : 1.0, kp);
+                    const kep::PairCoef c = kep::kepler_flow(live ? tau : 0.0, mu, x0, x1, x2,
+                                                             w0, w1, w2, live ? r0sq : 1.0, kp);
                     f.fm1 = c.fm1;
                     f.gmt = c.gmt;
                     f.fdot = c.fdot;
                     f.gdm1 = c.gdm1;
-                    f.iters = c.iters;
-                    f.converged = !(c.status & 1u);
-                    f.safeguarded = (c.status & 0x100u) != 0;
+                    info = ((unsigned)c.iters << 16) | c.status;
                 } else {
+                    const int ql = (q8 - base8) >> 3;
                     double s_net = __builtin_nan("");
                     if (MODE == 2) {
-                        const bool cand = live && kep::pair_may_qualify(net, tau, G * msum, r0sq);
+                        const bool cand = live && kep::pair_may_qualify(net, tau, mu, r0sq);
                         if (__any(cand))
-                            s_net = kep::net_starter(net, tau, cand ? G * msum : 0.0, x0, x1, x2,
-                                                     w0, w1, w2, r0sq);
+                            s_net = kep::net_starter(net, tau, cand ? mu : 0.0, x0, x1, x2, w0,
+                                                     w1, w2, r0sq);
                     }
                     kep::NetGuess<MODE, false> gp(net, (int)p, (int)(off + ql), s_net);
-                    f = kep::kepler_flow(live ? tau : 0.0, G * msum, x0, x1, x2, w0,
-                                         w1, w2, live ? r0sq : 1.0, kp, gp);
+                    f = kep::kepler_flow(live ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2,
+                                         live ? r0sq : 1.0, kp, gp);
                     if (live && gp.in_dom) {
                         ++dom_n;
                         dom_it += f.iters;
                     }
                     n_learned += (live && gp.used) ? 1u : 0u;
                     n_restart += (live && f.restarted) ? 1u : 0u;
+                    info = kep::pack_info(f.iters, f.converged, f.safeguarded);
                 }
                 if constexpr (!(MODE == 0 && DEFKP)) {
                     const double a = fma(-h, f.fdot, f.fm1);
@@ -195,22 +214,22 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                     d[4] = fma(f.fdot, x1, f.gdm1 * w1);
                     d[5] = fma(f.fdot, x2, f.gdm1 * w2);
                 }
-                // m_j / (m_i + m_j) and m_i / (m_i + m_j) times the flow's 1/mu;
-                // lanes without a pair have zero coefficients (they solve tau = 0)
-                const double wgt_i = G * mj, wgt_j = G * mi;
+                // m_j / (m_i + m_j) and m_i / (m_i + m_j) times the flow's 1/mu:
+                // G m_j and G m_i; lanes without a pair have zero increments
+                // (they solve tau = 0)
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    acc[c] = fma(wgt_i, d[c], acc[c]);
-                    sa[wv][c][q] = fma(-wgt_j, d[c], sa[wv][c][q]);
+                    acc[c] = fma(gmj, d[c], acc[c]);
+                    SA(c) = fma(-gmi, d[c], SA(c));
                 }
-                if (live) {
-                    ++n_solve;
-                    it_sum += f.iters;
-                    it_max = max(it_max, (unsigned)f.iters);
-                    n_fb += f.safeguarded ? 1u : 0u;
-                    if (!f.converged) flags |= ST_NOCONV;
-                }
-                if (collide) flags |= ST_COLLIDE;
+#undef SJ
+#undef SA
+                n_live += live ? 1u : 0u;
+                info_sum += info;
+                info_max = max(info_max, info);
+                coll_lane = coll_lane | collide;
+                q8 += inc8;
+                q8 = q8 >= lim8 ? q8 - L8 : q8;
                 // j-side sums of this sub-step visible to the next (with two
                 // wavefronts taking different numbers of sub-steps there is no
                 // workgroup barrier here: the wavefront's LDS operations complete
@@ -218,6 +237,13 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
                 if constexpr (WAVES == 1) __syncthreads();
                 else asm volatile("" ::: "memory");
             }
+            // the step's outcomes (at most 32 sub-steps: the fields stay apart)
+            n_sub += nsub_w;
+            it_all += info_sum >> 16;
+            n_fb += (info_sum >> 8) & 0xffu;
+            it_max_all = max(it_max_all, info_max >> 16);
+            unsigned flags = (info_sum & 0xffu) ? ST_NOCONV : 0u;
+            if (coll_lane) flags |= ST_COLLIDE;
             double jside[6];
             if constexpr (WAVES == 1) {
                 for (int c = 0; c < 6; ++c) jside[c] = sa[0][c][lane];
@@ -247,7 +273,6 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
             }
             if (valid && !fin) flags |= ST_NONFINITE;
             if (flags) record_error(cnt, flags, step);
-            flags = 0;
         }
         if (valid && wv == 0) {
             for (int c = 0; c < 3; ++c) {
@@ -256,10 +281,11 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
             }
         }
     }
-    n_solve = wave_sum(n_solve);
-    it_sum = wave_sum(it_sum);
+    // the trivial solves (one evaluation each) taken off
+    const unsigned n_solve = wave_sum(n_live);
+    const unsigned it_sum = wave_sum(it_all) - (TILE * n_sub - n_solve);
     n_fb = wave_sum(n_fb);
-    it_max = wave_max(it_max);
+    const unsigned it_max = n_solve ? wave_max(it_max_all) : 0u;
     GuessCount gc;
     if (MODE != 0) {
         gc.dom = wave_sum(dom_n);
