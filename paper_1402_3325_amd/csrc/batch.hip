@@ -737,8 +737,8 @@ int sakura_autotune_batch(sakura_t *h, int64_t nsys, const int64_t *offsets, con
             if (n >= BUCKET_LO[b] && n <= BUCKET_HI[b]) present[b] = true;
     }
     // Probes launch directly (a graph captured anew for every probe setting
-    // was tried and its test crashed the host process once, cause not found;
-    // see the design notes), coordinate by coordinate: the grid size with the
+    // was tried and its test crashed the host process once, cause not found),
+    // coordinate by coordinate: the grid size with the
     // current packing, then each present bucket's packing policy with the
     // others kept.
     const int reps = 2;
