@@ -3,7 +3,7 @@
 //
 // Each system is handled by a group of L lanes (L >= n, chosen per system size
 // by a policy table that sakura_autotune_batch can tune); a wavefront holds
-// floor(64 / L) systems of equal size.  Within a group the pairs follow the
+// groups of any sizes, placed by best fit.  Within a group the pairs follow the
 // same diagonal schedule as the tile kernel: in sub-step s lane l meets slot
 // (l + s) mod L, s = 1 .. floor((L - 1) / 2) plus, for even L, s = L/2 on the
 // lower half of the lanes, which visits each unordered pair once.  The
@@ -35,11 +35,14 @@ namespace {
 using namespace sk;
 
 struct WorkItem {
-    int first; // index into the sorted system order
+    int row;   // the item's row of the lane table
     int count; // systems in this item
-    int L;     // lanes per system
+    int nsub;  // sub-steps per step: those of its largest group
     int pad;
 };
+// One row of 64 entries per item: lane -> (system, l | L << 8), system -1 for a
+// lane without one.  A system of n particles takes L >= n consecutive lanes
+// (its group), l the lane's place in it; groups of different sizes share an item.
 
 // MODE selects the starter as in the tile kernel (0 plain, 1 domain
 // statistics, 2 the network's starter, 3 harvest rows); WAVES (1, 2 or 4)
@@ -49,7 +52,7 @@ struct WorkItem {
 template <int MODE, int WAVES, bool DEFKP = false>
 __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 4 : 1))) void k_batch(int nitems,
                                                         const WorkItem *__restrict__ items,
-                                                const int *__restrict__ order,
+                                                const int2 *__restrict__ lanes,
                                                 const int64_t *__restrict__ offsets,
                                                 const double *__restrict__ m,
                                                 const double *__restrict__ r,
@@ -89,11 +92,12 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
         item = __builtin_amdgcn_readfirstlane(item); // the item's fields in scalar registers
         if (item >= nitems) break;
         const WorkItem w = items[item];
-        const int L = w.L;
-        const int g = lane / L, l = lane - g * L;
-        const bool lane_in_tile = g < TILE / L; // lanes past the last full group idle
-        const bool in_group = g < w.count && lane_in_tile;
-        const int sys = in_group ? order[w.first + g] : 0;
+        const int2 lt = lanes[(size_t)w.row * TILE + lane];
+        const bool in_group = lt.x >= 0;
+        // a lane without a system is a group of one (its own slot)
+        const int L = in_group ? (lt.y >> 8) : 1;
+        const int l = in_group ? (lt.y & 0xff) : 0;
+        const int sys = in_group ? lt.x : 0;
         const int64_t off = in_group ? offsets[sys] : 0;
         const int nsys_n = in_group ? (int)(offsets[sys + 1] - off) : 0;
         const bool valid = in_group && l < nsys_n;
@@ -101,15 +105,17 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
         const double h = 0.5 * tau;
         const int64_t p = off + l;
         // Byte offset q8 of the partner's slot, (l + s) mod L within the lane's
-        // group, stepped with s (lanes past the last group keep their own slot:
-        // a group of one).  The partner holds a particle while q8 < valid8.
-        const int L8 = 8 * (lane_in_tile ? L : 1);
-        const int base8 = lane_in_tile ? 8 * (g * L) : 8 * lane;
+        // group, stepped with s.  The partner holds a particle while
+        // q8 < valid8.  The lane takes sub-steps s <= last_s: its group's
+        // floor((L - 1) / 2), plus for even L the middle one s = L/2 on the lower
+        // half of the group (the item runs to its largest group's count).
+        const int L8 = 8 * L;
+        const int base8 = 8 * (lane - l);
         const int lim8 = base8 + L8;
-        const int inc8 = lane_in_tile ? 8 * (WAVES % L) : 0;
-        const int q8_first = lane_in_tile ? base8 + 8 * ((l + 1 + wv) % L) : base8;
+        const int inc8 = 8 * (WAVES % L);
+        const int q8_first = base8 + 8 * ((l + 1 + wv) % L);
         const int valid8 = base8 + 8 * nsys_n;
-        const bool upper = 2 * l >= L; // even L: the middle sub-step is the lower half's
+        const int last_s = in_group ? (L - 1) / 2 + ((L & 1) == 0 && 2 * l < L ? 1 : 0) : 0;
         double mi = 0.0, x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
         if (valid) {
             mi = m[p];
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
             if (!fin) record_error(cnt, ST_NONFINITE, 0);
             else if (!(mi >= 0.0)) record_error(cnt, ST_INVAL, 0);
         }
-        const int nsub = (L - 1) / 2 + ((L & 1) ? 0 : 1);
+        const int nsub = w.nsub;
         // sub-steps this wavefront takes per step: s = 1 + wv, 1 + wv + WAVES, ...
         const unsigned nsub_w = nsub > wv ? (unsigned)((nsub - 1 - wv) / WAVES + 1) : 0u;
         const double gmi = G * mi; // the masses as G m (mi is 0 where !valid)
@@ -152,8 +158,7 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
 #define SA(c) (*(double *)((char *)sa[wv][c] + q8))
                 const double gmj = SJ(6);
                 const double mu = gmi + gmj;
-                const bool act = valid && q8 < valid8 && mu > 0.0 &&
-                                 !((L & 1) == 0 && 2 * s == L && upper);
+                const bool act = valid && q8 < valid8 && mu > 0.0 && s <= last_s;
                 const double w0 = u[0] - SJ(3), w1 = u[1] - SJ(4), w2 = u[2] - SJ(5);
                 const double x0 = fma(-h, w0, xh[0] - SJ(0));
                 const double x1 = fma(-h, w1, xh[1] - SJ(1));
@@ -301,12 +306,12 @@ __global__ __launch_bounds__(TILE * WAVES) __attribute__((amdgpu_waves_per_eu(MO
 
 template <int WAVES>
 void launch_batch_w(int mode, int grid, hipStream_t st, int nitems, const WorkItem *items,
-                    const int *order, const int64_t *offsets, const double *m, const double *r,
+                    const int2 *lanes, const int64_t *offsets, const double *m, const double *r,
                     const double *v, const double *dt, double *staged, int64_t ntot,
                     long long nsteps, double G, DevCounters *cnt, SlotStats *slots,
                     kep::KeplerParams kp, const kep::GuessNet &net, unsigned *queue)
 {
-#define SAKURA_BATCH_ARGS nitems, items, order, offsets, m, r, v, dt, staged, ntot, nsteps, G, \
+#define SAKURA_BATCH_ARGS nitems, items, lanes, offsets, m, r, v, dt, staged, ntot, nsteps, G, \
                           cnt, slots, kp, net, queue
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
     switch (mode) {
@@ -323,19 +328,19 @@ void launch_batch_w(int mode, int grid, hipStream_t st, int nitems, const WorkIt
 // The three launches: the items of four, two and one wavefronts (n[0], n[1],
 // n[2] items, in that order in the item list) on st[0], st[1], st[2].
 void launch_batch(int mode, const int grid[3], const hipStream_t st[3], const int n[3],
-                  const WorkItem *items, const int *order, const int64_t *offsets,
+                  const WorkItem *items, const int2 *lanes, const int64_t *offsets,
                   const double *m, const double *r, const double *v, const double *dt,
                   double *staged, int64_t ntot, long long nsteps, double G, DevCounters *cnt,
                   SlotStats *slots, kep::KeplerParams kp, const kep::GuessNet &net)
 {
     if (n[0])
-        launch_batch_w<4>(mode, grid[0], st[0], n[0], items, order, offsets, m, r, v, dt,
+        launch_batch_w<4>(mode, grid[0], st[0], n[0], items, lanes, offsets, m, r, v, dt,
                           staged, ntot, nsteps, G, cnt, slots, kp, net, &cnt->work_next4);
     if (n[1])
-        launch_batch_w<2>(mode, grid[1], st[1], n[1], items + n[0], order, offsets, m, r, v, dt,
+        launch_batch_w<2>(mode, grid[1], st[1], n[1], items + n[0], lanes, offsets, m, r, v, dt,
                           staged, ntot, nsteps, G, cnt, slots, kp, net, &cnt->work_next2);
     if (n[2])
-        launch_batch_w<1>(mode, grid[2], st[2], n[2], items + n[0] + n[1], order, offsets, m,
+        launch_batch_w<1>(mode, grid[2], st[2], n[2], items + n[0] + n[1], lanes, offsets, m,
                           r, v, dt, staged, ntot, nsteps, G, cnt, slots, kp, net,
                           &cnt->work_next);
 }
@@ -423,47 +428,77 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     if (nsteps == 0) return SAKURA_OK;
     const int64_t ntot = offsets[nsys];
 
-    // Work items: systems sorted by size (largest first), equal sizes packed
-    // floor(64 / L) to a wavefront; items of more than 32 lanes go to the
-    // four-wavefront launch, of 17..32 lanes to the two-wavefront one.
-    std::vector<int> order((size_t)nsys);
-    for (int64_t s = 0; s < nsys; ++s) order[(size_t)s] = (int)s;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
-    });
-    std::vector<int> items; // 4 ints per item
-    for (size_t k = 0; k < order.size();) {
-        const int n = (int)(offsets[order[k] + 1] - offsets[order[k]]);
-        const int ov = h->opts.tile_override;
-        const int L = ov > 0 ? std::max(n, ov) : std::max(n, std::min(TILE, h->batch_group[n]));
-        const int per = TILE / L;
-        size_t e = k;
-        while (e < order.size() && e - k < (size_t)per &&
-               offsets[order[e] + 1] - offsets[order[e]] == n)
-            ++e;
-        items.push_back((int)k);
-        items.push_back((int)(e - k));
-        items.push_back(L);
-        items.push_back(0);
-        k = e;
+    // Work items: each system takes L >= n consecutive lanes (its group; the
+    // handle's lane policy), and the systems, largest group first, are placed
+    // by best fit on the lanes still free in the open items, so that groups of
+    // different sizes share a wavefront.  An item runs to its largest group's
+    // sub-step count and goes to the launch of that group's width (four, two or
+    // one wavefronts per item); the items of each launch stay in the order they
+    // were opened, largest first.
+    const int ov = h->opts.tile_override;
+    std::vector<int> Ls((size_t)nsys), order((size_t)nsys);
+    for (int64_t s = 0; s < nsys; ++s) {
+        const int n = (int)(offsets[s + 1] - offsets[s]);
+        Ls[(size_t)s] = ov > 0 ? std::max(n, std::min(TILE, ov))
+                               : std::max(n, std::min(TILE, h->batch_group[n]));
+        order[(size_t)s] = (int)s;
     }
-    const int nitems = (int)(items.size() / 4);
-    // items of 4, 2 and 1 wavefronts, in that order, each group in size order
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return Ls[(size_t)a] > Ls[(size_t)b]; });
+    std::vector<int> bin_of((size_t)nsys), bin_free, bin_nsub, bin_big;
+    std::vector<int> by_free[TILE]; // open items by their free lanes (1 .. 63)
+    for (const int sy : order) {
+        const int L = Ls[(size_t)sy];
+        int bin = -1;
+        for (int f = L; f < TILE && bin < 0; ++f)
+            if (!by_free[f].empty()) {
+                bin = by_free[f].back();
+                by_free[f].pop_back();
+            }
+        if (bin < 0) { // a new item: this group is its largest
+            bin = (int)bin_free.size();
+            bin_free.push_back(TILE);
+            bin_nsub.push_back((L - 1) / 2 + ((L & 1) ? 0 : 1));
+            bin_big.push_back((int)(offsets[sy + 1] - offsets[sy]));
+        }
+        bin_free[(size_t)bin] -= L;
+        bin_of[(size_t)sy] = bin;
+        if (bin_free[(size_t)bin] > 0) by_free[bin_free[(size_t)bin]].push_back(bin);
+    }
+    const int nitems = (int)bin_free.size();
+    // the lane table: (system, l | L << 8) per lane, (-1, 0) on free lanes
+    std::vector<int> lane_tab((size_t)nitems * TILE * 2);
+    for (size_t e = 0; e < lane_tab.size(); e += 2) {
+        lane_tab[e] = -1;
+        lane_tab[e + 1] = 0;
+    }
+    std::vector<int> fill((size_t)nitems, 0), count((size_t)nitems, 0);
+    for (const int sy : order) {
+        const int bin = bin_of[(size_t)sy], L = Ls[(size_t)sy];
+        for (int l = 0; l < L; ++l) {
+            const size_t e = ((size_t)bin * TILE + (size_t)(fill[(size_t)bin] + l)) * 2;
+            lane_tab[e] = sy;
+            lane_tab[e + 1] = l | (L << 8);
+        }
+        fill[(size_t)bin] += L;
+        ++count[(size_t)bin];
+    }
+    // items of 4, 2 and 1 wavefronts, in that order
     int nw[3] = {0, 0, 0};
-    std::vector<int> grouped;
-    grouped.reserve(items.size());
+    std::vector<int> items;
+    items.reserve(4 * (size_t)nitems);
     for (int cls = 0; cls < 3; ++cls)
-        for (int k = 0; k < nitems; ++k) {
-            const int *it = &items[4 * (size_t)k];
-            const int n = (int)(offsets[order[(size_t)it[0]] + 1] - offsets[order[(size_t)it[0]]]);
-            const int w = batch_width(h, n);
+        for (int bin = 0; bin < nitems; ++bin) {
+            const int w = batch_width(h, bin_big[(size_t)bin]);
             if ((w == 4 ? 0 : (w == 2 ? 1 : 2)) != cls) continue;
-            grouped.insert(grouped.end(), it, it + 4);
+            items.push_back(bin);
+            items.push_back(count[(size_t)bin]);
+            items.push_back(bin_nsub[(size_t)bin]);
+            items.push_back(0);
             ++nw[cls];
         }
-    items.swap(grouped);
     h->host_work.assign(items.begin(), items.end());
-    h->host_work.insert(h->host_work.end(), order.begin(), order.end());
+    h->host_work.insert(h->host_work.end(), lane_tab.begin(), lane_tab.end());
 
     SAKURA_HIP(h, hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
@@ -496,7 +531,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     const int mode = guess_mode(h, &net);
     if (mode < 0) return fail(h, SAKURA_ENOMODEL, "learned starter requested but no model is loaded");
     const WorkItem *witems = reinterpret_cast<const WorkItem *>(h->batch_work);
-    const int *worder = h->batch_work + 4 * nitems;
+    const int2 *wlanes = reinterpret_cast<const int2 *>(h->batch_work + 4 * nitems);
     const unsigned eblocks = (unsigned)((3 * ntot + 255) / 256);
 
     // The launch sequence is captured once into a graph (on a private stream)
@@ -531,7 +566,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
             SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
             SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
             const hipStream_t bst[3] = {h->capture_stream, h->capture_stream2, h->capture_stream3};
-            launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
+            launch_batch(mode, wgrid, bst, nw, witems, wlanes, h->batch_offsets, m, r, v, dt,
                          h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
             SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
             SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
@@ -570,7 +605,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream2, h->graph_fork, 0));
         SAKURA_HIP(h, hipStreamWaitEvent(h->capture_stream3, h->graph_fork, 0));
         const hipStream_t bst[3] = {st, h->capture_stream2, h->capture_stream3};
-        launch_batch(mode, wgrid, bst, nw, witems, worder, h->batch_offsets, m, r, v, dt,
+        launch_batch(mode, wgrid, bst, nw, witems, wlanes, h->batch_offsets, m, r, v, dt,
                      h->batch_state, ntot, (long long)nsteps, G, h->cnt, h->slots, kp, net);
         SAKURA_HIP(h, hipEventRecord(h->graph_join, h->capture_stream2));
         SAKURA_HIP(h, hipEventRecord(h->graph_join2, h->capture_stream3));
