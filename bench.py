@@ -43,6 +43,7 @@ KERNEL_FLOPS_PER_EXTRA_ITER = 92
 KERNEL_SOURCES = ["paper_1402_3325_amd/csrc/kepler_device.hpp",
                   "paper_1402_3325_amd/csrc/guess_device.hpp",
                   "paper_1402_3325_amd/csrc/common.hpp",
+                  "paper_1402_3325_amd/csrc/tiles.hpp",
                   "paper_1402_3325_amd/csrc/sakura.hip"]
 # domain of the learned starter: tau' in [0.25, 64], b' >= -1, |e'| <= 3 (pairs the
 # plain starter needs three or more Kepler evaluations for)

@@ -9,6 +9,7 @@ LIB = os.path.join(HERE, "libsakura.so")
 SOURCES = [os.path.join(CSRC, "sakura.hip"), os.path.join(CSRC, "batch.hip"),
            os.path.join(CSRC, "guess.hip")]
 HEADERS = [os.path.join(CSRC, "kepler_device.hpp"), os.path.join(CSRC, "common.hpp"),
+           os.path.join(CSRC, "guess_device.hpp"), os.path.join(CSRC, "tiles.hpp"),
            os.path.join(os.path.dirname(HERE), "include", "sakura.h")]
 
 HIPCC_FLAGS = [

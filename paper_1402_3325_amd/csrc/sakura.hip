@@ -11,6 +11,7 @@
 // runs one such pair of launches per stage.  k_import / k_export convert
 // between the caller's [n][3] arrays and the internal layout once per call.
 #include "common.hpp"
+#include "tiles.hpp"
 
 #include <algorithm>
 #include <mutex>
@@ -126,22 +127,6 @@ __global__ void k_import(int n, int np, const double *__restrict__ m,
     }
 }
 
-// Blocks (I, J), I <= J, of tile t: off-diagonal tiles first (twice the work
-// of a diagonal one), column by column, then the diagonal.
-__device__ inline void tile_blocks(int t, int nb, int &I, int &J)
-{
-    const int noff = nb * (nb - 1) / 2;
-    if (t < noff) {
-        int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
-        while (j * (j - 1) / 2 > t) --j;
-        while ((j + 1) * j / 2 <= t) ++j;
-        J = j;
-        I = t - j * (j - 1) / 2;
-    } else {
-        I = J = t - noff;
-    }
-}
-
 // The plain solve of one pair: with HIST the diagnostic copy that also
 // evaluates the Kepler equation once more at the root (relative residual);
 // otherwise the copy with the default parameters built in (DEFKP) or the
@@ -214,7 +199,8 @@ template <bool B> struct BoolTag {
 };
 
 template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false, int SPLIT = 1>
-__global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np, double tau,
+__global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np,
+                                                StripLayout strips, double tau,
                                                 double cb, double ca, double G,
                                                 double e2, double e4,
                                                 const double *__restrict__ S,
@@ -233,9 +219,18 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         __syncthreads();
         if (s_stop) return;
     }
-    int I, J;
-    tile_blocks(blockIdx.x, nb, I, J);
-    const bool diag = (I == J);
+    // the work item: tiles (I, J0), ..., (I, J0 + len - 1).  Strips of several
+    // tiles need SPLIT 1 (with SPLIT > 1 the wavefronts combine their i-side
+    // sums in LDS per tile) and a mode other than 4 (whose deferred-pair list
+    // belongs to one tile).
+    int I, J0, len;
+    layout_item(blockIdx.x, nb, (SPLIT == 1 && MODE != 4) ? strips : StripLayout{1, 0}, I, J0,
+                len);
+    // uniform: the decoding's divisions and square root run on the vector ALU,
+    // and values left there would keep the sub-step counter there too
+    I = __builtin_amdgcn_readfirstlane(I);
+    J0 = __builtin_amdgcn_readfirstlane(J0);
+    len = __builtin_amdgcn_readfirstlane(len);
     static_assert(SPLIT == 1 || MODE != 4, "the deferred-pair list is one wavefront's");
     const int lane = SPLIT == 1 ? (int)threadIdx.x : (int)threadIdx.x % TILE;
     const int wv = SPLIT == 1 ? 0 : (int)threadIdx.x / TILE;
@@ -246,37 +241,25 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
 
     __shared__ double sj[7][TILE];          // x y z vx vy vz G m of block J (read only)
     __shared__ double sjs[SPLIT][6][TILE];  // j-side sums, by wavefront and slot of block J
-    __shared__ double sacc[SPLIT > 1 ? SPLIT - 1 : 1][6][TILE]; // i-side sums of wavefronts 1..
+    // i-side sums of wavefronts 1.. (SPLIT > 1); with SPLIT 1 the i-side sums of
+    // a strip's earlier tiles, each lane its own slots
+    __shared__ double sacc[SPLIT > 1 ? SPLIT - 1 : 1][6][TILE];
     __shared__ unsigned shist[HIST ? 32 : 1];
 
-    const int jg = J * TILE + lane;
     const int ig = I * TILE + lane;
-    if (wv == 0) {
-        sj[0][lane] = XH[jg];
-        sj[1][lane] = XH[np + jg];
-        sj[2][lane] = XH[2 * (size_t)np + jg];
-        sj[3][lane] = V[jg];
-        sj[4][lane] = V[np + jg];
-        sj[5][lane] = V[2 * (size_t)np + jg];
-        sj[6][lane] = G * M[jg];
-    }
     // particle i and its sums stay in registers.  The masses are held as G m:
     // mu = G m_i + G m_j (G (m_i + m_j) up to its rounding, equal for G = 1)
     // and the weights G m_j, G m_i of the increments per unit mu are read as
     // they are.
     const double xi[7] = {XH[ig], XH[np + ig], XH[2 * (size_t)np + ig], V[ig], V[np + ig],
                           V[2 * (size_t)np + ig], G * M[ig]};
-    double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sjs[wv][c][lane] = 0.0;
     if (HIST && wv == 0 && lane < 32) shist[lane] = 0;
 
     const bool valid_i = ig < n;
     const double wgt_j = xi[6];
     const double q4 = MODE == 4 ? kep::may_qualify_scale(net, tau) : 0.0;
     const double t2 = tau * tau, mtau = -tau; // MODE 5
-    const int nj = n - J * TILE; // valid j slots in this block
-    const int nj8 = 8 * nj, lane8 = 8 * lane;
+    const int lane8 = 8 * lane;
 
     // Every lane solves a pair in every sub-step (lanes without one solve
     // tau = 0: one evaluation, converged, never safeguarded), so the outcomes
@@ -290,260 +273,296 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     unsigned long long coll_bits = 0;    // per wave: lanes that met a zero separation
     bool coll_lane = false;              // HALVES: per lane, a zero separation met
     float rmax = 0.0f;                   // per lane, HIST: largest relative Kepler residual
-    __syncthreads();
+    int nsub_w = 0;                      // sub-steps this wavefront took, over the item
+    // tau held in a vector register, where the selection of the time passed to
+    // the solver reads it (from a scalar register it is moved there first, two
+    // more vector operations per pair)
+    double tau_v = tau;
+    asm volatile("" : "+v"(tau_v));
 
-    const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
-    // The sub-step loop in two copies: FULL for tiles whose 64 i and 64 j
-    // slots all hold particles of positive mass (every tile but those of the
-    // last block, in a system without massless particles), which need no test
-    // of the slots or of mu > 0.
-    const bool full_tile = (I + 1) * TILE <= n && (J + 1) * TILE <= n &&
-                           __all(xi[6] > 0.0 && sj[6][lane] > 0.0);
-    auto sweep = [&](auto full_tag) __attribute__((always_inline)) {
-    constexpr bool FULL = decltype(full_tag)::value;
-    int p8 = lane8 + 8 * (s0 + wv); // lane8 + 8 s, stepped with s
-    for (int s = s0 + wv; s < s1; s += SPLIT, p8 += 8 * SPLIT) {
-        // q scaled by 8 (the byte offset of slot q in a row of doubles) is
-        // formed and tested directly: one vector operation less than q itself.
-        // p8 is kept opaque, so that q8 stays one mask of it (left to itself
-        // the compiler forms ((lane + s) & 63) << 3 where q8 is not tested).
-        asm volatile("" : "+v"(p8));
-        const int q8 = p8 & (8 * (TILE - 1));
-        const int q = q8 >> 3;
-        // slot q of a row of block J and of this wavefront's j-side sums, by
-        // its byte offset (indexing by q has the compiler form q, then q8 again)
+    for (int J = J0; J < J0 + len; ++J) {
+        const bool diag = (I == J);
+        const int jg = J * TILE + lane;
+        if (J != J0) __syncthreads(); // the previous tile's reads of sj and sjs are done
+        if (wv == 0) {
+            sj[0][lane] = XH[jg];
+            sj[1][lane] = XH[np + jg];
+            sj[2][lane] = XH[2 * (size_t)np + jg];
+            sj[3][lane] = V[jg];
+            sj[4][lane] = V[np + jg];
+            sj[5][lane] = V[2 * (size_t)np + jg];
+            sj[6][lane] = G * M[jg];
+        }
+        double ai[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sjs[wv][c][lane] = 0.0;
+        const int nj = n - J * TILE; // valid j slots in this block
+        const int nj8 = 8 * nj;
+        __syncthreads();
+
+        const int s0 = diag ? 1 : 0, s1 = diag ? (TILE / 2 + 1) : TILE;
+        // The sub-step loop in two copies: FULL for tiles whose 64 i and 64 j
+        // slots all hold particles of positive mass (every tile but those of the
+        // last block, in a system without massless particles), which need no test
+        // of the slots or of mu > 0.
+        const bool full_tile = (I + 1) * TILE <= n && (J + 1) * TILE <= n &&
+                               __all(xi[6] > 0.0 && sj[6][lane] > 0.0);
+        auto sweep = [&](auto full_tag) __attribute__((always_inline)) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        int p8 = lane8 + 8 * (s0 + wv); // lane8 + 8 s, stepped with s
+        for (int s = s0 + wv; s < s1; s += SPLIT, p8 += 8 * SPLIT) {
+            // q scaled by 8 (the byte offset of slot q in a row of doubles) is
+            // formed and tested directly: one vector operation less than q itself.
+            // p8 is kept opaque, so that q8 stays one mask of it (left to itself
+            // the compiler forms ((lane + s) & 63) << 3 where q8 is not tested).
+            asm volatile("" : "+v"(p8));
+            const int q8 = p8 & (8 * (TILE - 1));
+            const int q = q8 >> 3;
+            // slot q of a row of block J and of this wavefront's j-side sums, by
+            // its byte offset (indexing by q has the compiler form q, then q8 again)
 #define SJ(c) (*(const double *)((const char *)sj[c] + q8))
 #define SJS(c) (*(double *)((char *)sjs[wv][c] + q8))
-        // In harvest mode the particle data are read from LDS at every use and
-        // the relative state is formed again after the solve (compiler-only
-        // fences): its inlined policy's extra live state would otherwise push
-        // the loop past 128 VGPRs.  The other modes keep it.
-        if (MODE == 3) asm volatile("" ::: "memory");
-        const double gmj = SJ(6);
-        const double mu = xi[6] + gmj;
-        const bool act = (FULL || (valid_i && (q8 < nj8) && (mu > 0.0))) &&
-                         !(diag && s == TILE / 2 && lane >= TILE / 2);
-        if constexpr (MODE == 5) {
-            const double X0 = xi[0] - SJ(0), X1 = xi[1] - SJ(1), X2 = xi[2] - SJ(2);
-            const double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4), w2 = xi[5] - SJ(5);
-            const double r2 = fma(X0, X0, fma(X1, X1, X2 * X2));
-            const double ws = fma(w0, w0, fma(w1, w1, w2 * w2));
-            const bool close = act & hybrid_close(t2, mu, r2, ws, e2, e4);
-            // eq. (28): the relative velocity changes by tau a_ij at X and the
-            // position increment vanishes; per unit mu, dv = -tau X / r^3
-            const bool kick = act & !close & (r2 > 0.0);
-            bool collide = act & !close & !(r2 > 0.0);
-            const double rinv = kep::rsqrt_refined(r2); // used only where kick holds
-            const double kf = kick ? mtau * (rinv * rinv * rinv) : 0.0;
-            const double wgt_i = gmj;
-            if (!__builtin_amdgcn_ballot_w64(close)) {
-                // no close pair in this sub-step: velocity sums only, weights
-                // folded into the kick
-                const double ki = wgt_i * kf, kj = -wgt_j * kf;
-                ai[3] = fma(ki, X0, ai[3]);
-                ai[4] = fma(ki, X1, ai[4]);
-                ai[5] = fma(ki, X2, ai[5]);
-                SJS(3) = fma(kj, X0, SJS(3));
-                SJS(4) = fma(kj, X1, SJS(4));
-                SJS(5) = fma(kj, X2, SJS(5));
-            } else {
-                // the Kepler map of eq. (26), as in MODE 0, for the close lanes
-                double d[6] = {0.0, 0.0, 0.0, kf * X0, kf * X1, kf * X2};
-                const double x0 = fma(-cb, w0, X0), x1 = fma(-cb, w1, X1), x2 = fma(-cb, w2, X2);
-                const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
-                const bool kl = close && (r0sq > 0.0);
-                collide = collide || (close && !(r0sq > 0.0));
+            // In harvest mode the particle data are read from LDS at every use and
+            // the relative state is formed again after the solve (compiler-only
+            // fences): its inlined policy's extra live state would otherwise push
+            // the loop past 128 VGPRs.  The other modes keep it.
+            if (MODE == 3) asm volatile("" ::: "memory");
+            const double gmj = SJ(6);
+            const double mu = xi[6] + gmj;
+            const bool act = (FULL || (valid_i && (q8 < nj8) && (mu > 0.0))) &&
+                             !(diag && s == TILE / 2 && lane >= TILE / 2);
+            if constexpr (MODE == 5) {
+                const double X0 = xi[0] - SJ(0), X1 = xi[1] - SJ(1), X2 = xi[2] - SJ(2);
+                const double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4), w2 = xi[5] - SJ(5);
+                const double r2 = fma(X0, X0, fma(X1, X1, X2 * X2));
+                const double ws = fma(w0, w0, fma(w1, w1, w2 * w2));
+                const bool close = act & hybrid_close(t2, mu, r2, ws, e2, e4);
+                // eq. (28): the relative velocity changes by tau a_ij at X and the
+                // position increment vanishes; per unit mu, dv = -tau X / r^3
+                const bool kick = act & !close & (r2 > 0.0);
+                bool collide = act & !close & !(r2 > 0.0);
+                const double rinv = kep::rsqrt_refined(r2); // used only where kick holds
+                const double kf = kick ? mtau * (rinv * rinv * rinv) : 0.0;
+                const double wgt_i = gmj;
+                if (!__builtin_amdgcn_ballot_w64(close)) {
+                    // no close pair in this sub-step: velocity sums only, weights
+                    // folded into the kick
+                    const double ki = wgt_i * kf, kj = -wgt_j * kf;
+                    ai[3] = fma(ki, X0, ai[3]);
+                    ai[4] = fma(ki, X1, ai[4]);
+                    ai[5] = fma(ki, X2, ai[5]);
+                    SJS(3) = fma(kj, X0, SJS(3));
+                    SJS(4) = fma(kj, X1, SJS(4));
+                    SJS(5) = fma(kj, X2, SJS(5));
+                } else {
+                    // the Kepler map of eq. (26), as in MODE 0, for the close lanes
+                    double d[6] = {0.0, 0.0, 0.0, kf * X0, kf * X1, kf * X2};
+                    const double x0 = fma(-cb, w0, X0), x1 = fma(-cb, w1, X1),
+                                 x2 = fma(-cb, w2, X2);
+                    const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+                    const bool kl = close && (r0sq > 0.0);
+                    collide = collide || (close && !(r0sq > 0.0));
+                    const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
+                        kl ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, kl ? r0sq : 1.0, kp);
+                    if (HIST && kl) rmax = fmaxf(rmax, (float)f.resid);
+                    if (kl) {
+                        const double a = fma(-ca, f.fdot, f.fm1);
+                        const double b = fma(-ca, f.gdm1, f.gmt);
+                        d[0] = fma(a, x0, b * w0);
+                        d[1] = fma(a, x1, b * w1);
+                        d[2] = fma(a, x2, b * w2);
+                        d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+                        d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+                        d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+                    }
+                    const unsigned info = kl ? (((unsigned)f.iters << 16) | f.status) : 0u;
+                    info_sum += info;
+                    info_max = max(info_max, info);
+                    n_solve += __popcll(__builtin_amdgcn_ballot_w64(kl));
+                    if (HIST && kl) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        ai[c] = fma(wgt_i, d[c], ai[c]);
+                        SJS(c) = fma(-wgt_j, d[c], SJS(c));
+                    }
+                }
+                n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
+                coll_bits |= __builtin_amdgcn_ballot_w64(collide);
+                continue;
+            }
+            // relative state and the pair back-drift of eq. (17) by cb
+            double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4),
+                   w2 = xi[5] - SJ(5);
+            double x0 = fma(-cb, w0, xi[0] - SJ(0));
+            double x1 = fma(-cb, w1, xi[1] - SJ(1));
+            double x2 = fma(-cb, w2, xi[2] - SJ(2));
+            const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
+            const bool collide = act && !(r0sq > 0.0);
+            bool live = act && !collide;
+            // lanes without a pair solve a trivial problem (tau = 0, |x0| = 1; any
+            // finite mu): the starter is s = 0, where t(s) = 0 holds at once
+            double d[6]; // increment of the pair map less the starting relative state, per unit mu
+            unsigned info;
+            if constexpr (MODE == 4) {
+                // Pairs that may lie in the network's domain (a necessary condition
+                // from the unreduced tau) are listed for k_deferred while the tile's
+                // list has room, and skipped here; the rest take the plain solve.
+                const bool cand = live & kep::pair_may_qualify_q(q4, mu, r0sq);
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64(cand);
+                if (mask) {
+                    const unsigned long long below =
+                        lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+                    const int rank = (int)__popcll(below), total = (int)__popcll(mask);
+                    if (cand && rank < room) {
+                        net.defer_pairs[(size_t)blockIdx.x * kep::DEFER_CAP +
+                                        (kep::DEFER_CAP - room) + rank] =
+                            make_int2(ig, J * TILE + q);
+                        live = false; // solved, and counted, by k_deferred
+                    }
+                    room = room > total ? room - total : 0;
+                }
+            }
+            if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
+                // The pairs solved are counted by a ballot of the time passed on
+                // (tau where a pair is solved, 0 elsewhere; tau != 0 is a condition
+                // of this path): the compiler forms a ballot of the combined lane
+                // predicate through two vector operations, of the comparison
+                // through one.  The collisions are tallied per lane.
+                double tsel = live ? tau_v : 0.0;
+                asm volatile("" : "+v"(tsel)); // keeps the comparison on tsel
+                n_solve += __popcll(__builtin_amdgcn_ballot_w64(tsel != 0.0));
+                coll_lane = coll_lane | collide;
+                // Lanes without a pair pass their own r0^2 with tau = 0, which the
+                // solve takes at s = 0 to zero increments for any finite positive
+                // r0^2; the floor keeps r0^2 = 0 (a collision, or a pair of
+                // coincident massless particles) finite in the solve.
+                const kep::PairMap pm = kep::kepler_map_halves(tsel, mu, x0, x1, x2, w0, w1, w2,
+                                                               fmax(r0sq, 0x1p-1022));
+                d[0] = pm.dx0;
+                d[1] = pm.dx1;
+                d[2] = pm.dx2;
+                d[3] = pm.dv0;
+                d[4] = pm.dv1;
+                d[5] = pm.dv2;
+                info = pm.info;
+            } else if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
                 const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
-                    kl ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, kl ? r0sq : 1.0, kp);
-                if (HIST && kl) rmax = fmaxf(rmax, (float)f.resid);
-                if (kl) {
-                    const double a = fma(-ca, f.fdot, f.fm1);
-                    const double b = fma(-ca, f.gdm1, f.gmt);
-                    d[0] = fma(a, x0, b * w0);
-                    d[1] = fma(a, x1, b * w1);
-                    d[2] = fma(a, x2, b * w2);
-                    d[3] = fma(f.fdot, x0, f.gdm1 * w0);
-                    d[4] = fma(f.fdot, x1, f.gdm1 * w1);
-                    d[5] = fma(f.fdot, x2, f.gdm1 * w2);
-                }
-                const unsigned info = kl ? (((unsigned)f.iters << 16) | f.status) : 0u;
-                info_sum += info;
-                info_max = max(info_max, info);
-                n_solve += __popcll(__builtin_amdgcn_ballot_w64(kl));
-                if (HIST && kl) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    ai[c] = fma(wgt_i, d[c], ai[c]);
-                    SJS(c) = fma(-wgt_j, d[c], SJS(c));
-                }
-            }
-            n_kick += __popcll(__builtin_amdgcn_ballot_w64(kick));
-            coll_bits |= __builtin_amdgcn_ballot_w64(collide);
-            continue;
-        }
-        // relative state and the pair back-drift of eq. (17) by cb
-        double w0 = xi[3] - SJ(3), w1 = xi[4] - SJ(4),
-               w2 = xi[5] - SJ(5);
-        double x0 = fma(-cb, w0, xi[0] - SJ(0));
-        double x1 = fma(-cb, w1, xi[1] - SJ(1));
-        double x2 = fma(-cb, w2, xi[2] - SJ(2));
-        const double r0sq = fma(x0, x0, fma(x1, x1, x2 * x2));
-        const bool collide = act && !(r0sq > 0.0);
-        bool live = act && !collide;
-        // lanes without a pair solve a trivial problem (tau = 0, |x0| = 1; any
-        // finite mu): the starter is s = 0, where t(s) = 0 holds at once
-        double d[6]; // increment of the pair map less the starting relative state, per unit mu
-        unsigned info;
-        if constexpr (MODE == 4) {
-            // Pairs that may lie in the network's domain (a necessary condition
-            // from the unreduced tau) are listed for k_deferred while the tile's
-            // list has room, and skipped here; the rest take the plain solve.
-            const bool cand = live & kep::pair_may_qualify_q(q4, mu, r0sq);
-            const unsigned long long mask = __builtin_amdgcn_ballot_w64(cand);
-            if (mask) {
-                const unsigned long long below =
-                    lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
-                const int rank = (int)__popcll(below), total = (int)__popcll(mask);
-                if (cand && rank < room) {
-                    net.defer_pairs[(size_t)blockIdx.x * kep::DEFER_CAP +
-                                    (kep::DEFER_CAP - room) + rank] = make_int2(ig, J * TILE + q);
-                    live = false; // solved, and counted, by k_deferred
-                }
-                room = room > total ? room - total : 0;
-            }
-        }
-        if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4)) {
-            // The pairs solved are counted by a ballot of the time passed on
-            // (tau where a pair is solved, 0 elsewhere; tau != 0 is a condition
-            // of this path): the compiler forms a ballot of the combined lane
-            // predicate through two vector operations, of the comparison
-            // through one.  The collisions are tallied per lane.
-            double tsel = live ? tau : 0.0;
-            asm volatile("" : "+v"(tsel)); // keeps the comparison on tsel
-            n_solve += __popcll(__builtin_amdgcn_ballot_w64(tsel != 0.0));
-            coll_lane = coll_lane | collide;
-            // Lanes without a pair pass their own r0^2 with tau = 0, which the
-            // solve takes at s = 0 to zero increments for any finite positive
-            // r0^2; the floor keeps r0^2 = 0 (a collision, or a pair of
-            // coincident massless particles) finite in the solve.
-            const kep::PairMap pm = kep::kepler_map_halves(tsel, mu, x0, x1, x2, w0, w1, w2,
-                                                           fmax(r0sq, 0x1p-1022));
-            d[0] = pm.dx0;
-            d[1] = pm.dx1;
-            d[2] = pm.dx2;
-            d[3] = pm.dv0;
-            d[4] = pm.dv1;
-            d[5] = pm.dv2;
-            info = pm.info;
-        } else if constexpr (MODE == 0 || MODE == 4 || MODE == 5) { // (MODE 5 never gets here)
-            const kep::PairCoefDiag f = solve_pair<HIST, DEFKP>(
-                live ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
-            if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
-            const double a = fma(-ca, f.fdot, f.fm1);
-            const double b = fma(-ca, f.gdm1, f.gmt);
-            d[0] = fma(a, x0, b * w0);
-            d[1] = fma(a, x1, b * w1);
-            d[2] = fma(a, x2, b * w2);
-            d[3] = fma(f.fdot, x0, f.gdm1 * w0);
-            d[4] = fma(f.fdot, x1, f.gdm1 * w1);
-            d[5] = fma(f.fdot, x2, f.gdm1 * w2);
-            info = ((unsigned)f.iters << 16) | f.status;
-        } else {
-            kep::PairFlow f;
-            if constexpr (MODE == 1) {
-                f = kep::kepler_flow_domain<HIST>(live ? tau : 0.0, mu, x0, x1, x2,
-                                                  w0, w1, w2, live ? r0sq : 1.0, kp,
-                                                  net.tau2_lo, net.tau2_hi, net.b_lo,
-                                                  net.e2_hi);
+                    live ? tau : 0.0, mu, x0, x1, x2, w0, w1, w2, live ? r0sq : 1.0, kp);
                 if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
-                const bool dom = live && f.in_dom;
-                gc.dom += __popcll(__ballot(dom));
-                dom_it += dom ? (unsigned)f.iters : 0u;
-            } else { // harvest
-                kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
-                f = kep::kepler_flow(live ? tau : 0.0, mu, x0, x1, x2, w0, w1,
-                                     w2, live ? r0sq : 1.0, kp, gp);
-                const bool dom = live && gp.in_dom;
-                gc.dom += __popcll(__ballot(dom));
-                dom_it += dom ? (unsigned)f.iters : 0u;
+                const double a = fma(-ca, f.fdot, f.fm1);
+                const double b = fma(-ca, f.gdm1, f.gmt);
+                d[0] = fma(a, x0, b * w0);
+                d[1] = fma(a, x1, b * w1);
+                d[2] = fma(a, x2, b * w2);
+                d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+                d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+                d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+                info = ((unsigned)f.iters << 16) | f.status;
+            } else {
+                kep::PairFlow f;
+                if constexpr (MODE == 1) {
+                    f = kep::kepler_flow_domain<HIST>(live ? tau : 0.0, mu, x0, x1, x2,
+                                                      w0, w1, w2, live ? r0sq : 1.0, kp,
+                                                      net.tau2_lo, net.tau2_hi, net.b_lo,
+                                                      net.e2_hi);
+                    if (HIST && live) rmax = fmaxf(rmax, (float)f.resid);
+                    const bool dom = live && f.in_dom;
+                    gc.dom += __popcll(__ballot(dom));
+                    dom_it += dom ? (unsigned)f.iters : 0u;
+                } else { // harvest
+                    kep::NetGuess<MODE> gp(net, ig, J * TILE + q);
+                    f = kep::kepler_flow(live ? tau : 0.0, mu, x0, x1, x2, w0, w1,
+                                         w2, live ? r0sq : 1.0, kp, gp);
+                    const bool dom = live && gp.in_dom;
+                    gc.dom += __popcll(__ballot(dom));
+                    dom_it += dom ? (unsigned)f.iters : 0u;
+                }
+                if (MODE == 3) { // the same relative state again, bitwise
+                    asm volatile("" ::: "memory");
+                    w0 = xi[3] - SJ(3);
+                    w1 = xi[4] - SJ(4);
+                    w2 = xi[5] - SJ(5);
+                    x0 = fma(-cb, w0, xi[0] - SJ(0));
+                    x1 = fma(-cb, w1, xi[1] - SJ(1));
+                    x2 = fma(-cb, w2, xi[2] - SJ(2));
+                }
+                const double a = fma(-ca, f.fdot, f.fm1);
+                const double b = fma(-ca, f.gdm1, f.gmt);
+                d[0] = fma(a, x0, b * w0);
+                d[1] = fma(a, x1, b * w1);
+                d[2] = fma(a, x2, b * w2);
+                d[3] = fma(f.fdot, x0, f.gdm1 * w0);
+                d[4] = fma(f.fdot, x1, f.gdm1 * w1);
+                d[5] = fma(f.fdot, x2, f.gdm1 * w2);
+                info = kep::pack_info(f.iters, f.converged, f.safeguarded);
             }
-            if (MODE == 3) { // the same relative state again, bitwise
-                asm volatile("" ::: "memory");
-                w0 = xi[3] - SJ(3);
-                w1 = xi[4] - SJ(4);
-                w2 = xi[5] - SJ(5);
-                x0 = fma(-cb, w0, xi[0] - SJ(0));
-                x1 = fma(-cb, w1, xi[1] - SJ(1));
-                x2 = fma(-cb, w2, xi[2] - SJ(2));
-            }
-            const double a = fma(-ca, f.fdot, f.fm1);
-            const double b = fma(-ca, f.gdm1, f.gmt);
-            d[0] = fma(a, x0, b * w0);
-            d[1] = fma(a, x1, b * w1);
-            d[2] = fma(a, x2, b * w2);
-            d[3] = fma(f.fdot, x0, f.gdm1 * w0);
-            d[4] = fma(f.fdot, x1, f.gdm1 * w1);
-            d[5] = fma(f.fdot, x2, f.gdm1 * w2);
-            info = kep::pack_info(f.iters, f.converged, f.safeguarded);
-        }
-        // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j),
-        // times mu = G (m_i + m_j) that the increments are divided by; lanes
-        // without a pair have zero increments (they solve tau = 0)
-        const double wgt_i = gmj;
+            // weights mu_ij / m_i = m_j / (m_i + m_j) and mu_ij / m_j = m_i / (m_i + m_j),
+            // times mu = G (m_i + m_j) that the increments are divided by; lanes
+            // without a pair have zero increments (they solve tau = 0)
+            const double wgt_i = gmj;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            ai[c] = fma(wgt_i, d[c], ai[c]);
-            SJS(c) = fma(-wgt_j, d[c], SJS(c));
+            for (int c = 0; c < 6; ++c) {
+                ai[c] = fma(wgt_i, d[c], ai[c]);
+                SJS(c) = fma(-wgt_j, d[c], SJS(c));
+            }
+            info_sum += info;
+            info_max = max(info_max, info);
+            if constexpr (!(HALVES && !HIST && (MODE == 0 || MODE == 4))) {
+                n_solve += __popcll(__builtin_amdgcn_ballot_w64(live));
+                coll_bits |= __builtin_amdgcn_ballot_w64(collide);
+            }
+            if (HIST && live) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
         }
-        info_sum += info;
-        info_max = max(info_max, info);
-        if constexpr (!(HALVES && !HIST && (MODE == 0 || MODE == 4))) {
-            n_solve += __popcll(__builtin_amdgcn_ballot_w64(live));
-            coll_bits |= __builtin_amdgcn_ballot_w64(collide);
-        }
-        if (HIST && live) atomicAdd(&shist[min(info >> 16, 31u)], 1u);
-    }
-    };
-    if (full_tile) sweep(BoolTag<true>{});
-    else sweep(BoolTag<false>{});
+        };
+        if (full_tile) sweep(BoolTag<true>{});
+        else sweep(BoolTag<false>{});
 #undef SJ
 #undef SJS
 
+        if constexpr (SPLIT > 1) {
+            if (wv > 0)
+                for (int c = 0; c < 6; ++c) sacc[wv - 1][c][lane] = ai[c];
+        }
+        __syncthreads();
+        if (wv == 0) {
+            // the wavefronts' sums in wavefront order (SPLIT 1: the sums as they are)
+            double aj[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                aj[c] = sjs[0][c][lane];
+#pragma unroll
+                for (int w = 1; w < SPLIT; ++w) {
+                    ai[c] += sacc[w - 1][c][lane];
+                    aj[c] += sjs[w][c][lane];
+                }
+            }
+            const size_t cs = TILE; // component stride inside a partial
+            if (!diag) {
+                double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
+                for (int c = 0; c < 6; ++c) pji[c * cs] = aj[c];
+            }
+            // the tile's i side (on the diagonal both sides are block I's): an item
+            // of one tile writes it; a strip adds it to its earlier tiles' sums, in
+            // tile order, and writes the total after its last tile
+            double *pij = part + ((size_t)I * nb + J0) * 6 * cs + lane;
+            for (int c = 0; c < 6; ++c) {
+                const double o = diag ? ai[c] + aj[c] : ai[c];
+                if (len == 1) {
+                    pij[c * cs] = o;
+                } else {
+                    const double acc = J == J0 ? o : sacc[0][c][lane] + o;
+                    if (J == J0 + len - 1) pij[c * cs] = acc;
+                    else sacc[0][c][lane] = acc;
+                }
+            }
+        }
+        // with SPLIT each wavefront counts the sub-steps it took
+        nsub_w += SPLIT == 1 ? s1 - s0 : (s1 - s0 - wv + SPLIT - 1) / SPLIT;
+    } // tiles of the item
+
     if constexpr (HALVES && !HIST && (MODE == 0 || MODE == 4))
         coll_bits = __builtin_amdgcn_ballot_w64(coll_lane);
-    if constexpr (SPLIT > 1) {
-        if (wv > 0)
-            for (int c = 0; c < 6; ++c) sacc[wv - 1][c][lane] = ai[c];
-    }
-    __syncthreads();
-    if (wv == 0) {
-        // the wavefronts' sums in wavefront order (SPLIT 1: the sums as they are)
-        double aj[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            aj[c] = sjs[0][c][lane];
-#pragma unroll
-            for (int w = 1; w < SPLIT; ++w) {
-                ai[c] += sacc[w - 1][c][lane];
-                aj[c] += sjs[w][c][lane];
-            }
-        }
-        const size_t cs = TILE; // component stride inside a partial
-        double *pij = part + ((size_t)I * nb + J) * 6 * cs + lane;
-        if (diag) {
-            for (int c = 0; c < 6; ++c) pij[c * cs] = ai[c] + aj[c];
-        } else {
-            double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
-            for (int c = 0; c < 6; ++c) {
-                pij[c * cs] = ai[c];
-                pji[c * cs] = aj[c];
-            }
-        }
-    }
-
-    // MODE 5 counts only the close lanes' solves; with SPLIT each wavefront
-    // counts the sub-steps it took
-    const int nsub_w = SPLIT == 1 ? s1 - s0 : (s1 - s0 - wv + SPLIT - 1) / SPLIT;
+    // MODE 5 counts only the close lanes' solves
     const unsigned trivial = MODE == 5 ? 0u : (unsigned)(TILE * nsub_w) - (unsigned)n_solve;
     const unsigned it_sum = wave_sum(info_sum >> 16) - trivial;
     const unsigned it_max = n_solve ? wave_max(info_max >> 16) : 0u;
@@ -670,12 +689,43 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
     }
 }
 
+// TwoSum of the partial-sum slots k0.. of one component into (s, e), in slot
+// order, B loads in flight per round.
+template <int B>
+__device__ inline void reduce_slots(const double *__restrict__ p, size_t stride, int nslot, int K,
+                                    int nb, StripLayout strips, double &s, double &e)
+{
+    int k0 = 0;
+    for (; k0 + B <= nslot; k0 += B) {
+        double x[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) x[k] = p[(size_t)apply_slot(k0 + k, K, nb, strips) * stride];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const double t = s + x[k];
+            const double bp = t - s;
+            e += (s - (t - bp)) + (x[k] - bp);
+            s = t;
+        }
+    }
+    for (; k0 < nslot; ++k0) {
+        const double x = p[(size_t)apply_slot(k0, K, nb, strips) * stride];
+        const double t = s + x;
+        const double bp = t - s;
+        e += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+}
+
 // Deterministic compensated reduction of the partial sums of one block K
-// (fixed order L = 0..nb-1, TwoSum), then eqs. (27b-d): the drift h_after
+// (fixed order: the j sides L = 0..K-1, then the i sides of row K in tile
+// order, one per work item of the pair launch with the layout `strips`;
+// L = 0..nb-1 with one tile per item; TwoSum), then eqs. (27b-d): the drift h_after
 // that ends the stage, and the drift h_next that begins the next one (27a of
 // the next step; both tau/2 for eq. 25).  Wave c of the workgroup reduces
 // component c.
-__global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, double h_after,
+__global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, StripLayout strips,
+                                                    double h_after,
                                                     double h_next,
                                                     double *__restrict__ S,
                                                     const double *__restrict__ part,
@@ -691,27 +741,13 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, doubl
     const double *p = part + ((size_t)K * nb * 6 + c) * TILE + lane;
     const size_t stride = 6 * TILE;
     double s = 0.0, e = 0.0;
-    int L = 0;
-    // eight loads in flight per round; the sum itself stays in order L = 0..nb-1
-    for (; L + 8 <= nb; L += 8) {
-        double x[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = p[(size_t)(L + k) * stride];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double t = s + x[k];
-            const double bp = t - s;
-            e += (s - (t - bp)) + (x[k] - bp);
-            s = t;
-        }
-    }
-    for (; L < nb; ++L) {
-        const double x = p[(size_t)L * stride];
-        const double t = s + x;
-        const double bp = t - s;
-        e += (s - (t - bp)) + (x - bp);
-        s = t;
-    }
+    const int nslot = apply_slots(K, nb, strips);
+    // With strips the blocks of the strip rows read fewer slots than those of
+    // the single-tile rows, which set the launch's length: 16 loads in flight
+    // shorten them (with every block reading nb slots the launch is bound by
+    // the memory, and 8 do better).
+    if (strips_on(strips)) reduce_slots<16>(p, stride, nslot, K, nb, strips, s, e);
+    else reduce_slots<8>(p, stride, nslot, K, nb, strips, s, e);
     dsum[c][lane] = s + e;
     __syncthreads();
     if (c != 0) return;
@@ -888,14 +924,37 @@ int pair_split(int ntiles, int cus)
     return split;
 }
 
-// One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one).
+// The work items of the pair launch for the plain kernel of one wavefront
+// per tile.  Strips of S tiles along a row write one i-side partial per strip
+// instead of one per tile (and start a wavefront once per strip), but a
+// launch cannot end before its longest item, and long items drain it
+// unevenly.  So the rows of the last blocks, a triangle of at least two
+// tiles per wavefront slot, stay single tiles, which the launch ends with,
+// and the rows before them are strips of 4 tiles (a strip then takes about
+// half of the launch at N = 16384; with 8 tiles, as long as the launch, the
+// launch took 10 % longer).  A requested S puts strips of S in every row.  Strips need
+// SPLIT 1 and a mode other than the deferred-pair list's (mode 2 here, 4 in
+// the kernel).
+StripLayout pair_strips(int requested, int split, int mode, int nb, int cus)
+{
+    if (split > 1 || mode == 2) return StripLayout{1, 0};
+    if (requested > 0) return StripLayout{std::min(requested, std::max(nb, 1)), nb};
+    const int64_t tail = 2 * (int64_t)cus * 16; // wavefront slots: 4 SIMDs x 4 wavefronts per CU
+    int64_t nt = 0;
+    while (nt < nb && nt * (nt + 1) / 2 < tail) ++nt;
+    return StripLayout{4, (int)(nb - nt)};
+}
+
+// One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one),
+// or one wavefront per strip of `strip` tiles (pair_strip).
 template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false>
-void launch_tiles(int split, int ntiles, hipStream_t st, int n, int nb, int np, double dt,
-                  double cb, double ca, double G, double e2, double e4, const double *S,
+void launch_tiles(int split, StripLayout strips, int ntiles, hipStream_t st, int n, int nb,
+                  int np, double dt, double cb, double ca, double G, double e2, double e4, const double *S,
                   double *part, DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp,
                   long long step, const kep::GuessNet &net)
 {
-#define SAKURA_PAIR_ARGS n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, net
+#define SAKURA_PAIR_ARGS n, nb, np, strips, dt, cb, ca, G, e2, e4, S, part, cnt, slots, kp, step, \
+                         net
     if constexpr (MODE != 4) {
         if (split == 4) {
             k_pairs<HIST, MODE, DEFKP, HALVES, 4><<<ntiles, 4 * TILE, 0, st>>>(SAKURA_PAIR_ARGS);
@@ -906,12 +965,14 @@ void launch_tiles(int split, int ntiles, hipStream_t st, int n, int nb, int np, 
             return;
         }
     }
-    k_pairs<HIST, MODE, DEFKP, HALVES, 1><<<ntiles, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
+    const int nitems = (int)layout_items(nb, strips);
+    k_pairs<HIST, MODE, DEFKP, HALVES, 1><<<nitems, TILE, 0, st>>>(SAKURA_PAIR_ARGS);
 #undef SAKURA_PAIR_ARGS
 }
 
 template <bool HIST>
-void launch_pairs_h(int mode, int split, int ntiles, hipStream_t st, int n, int nb, int np,
+void launch_pairs_h(int mode, int split, StripLayout strips, int ntiles, hipStream_t st, int n, int nb,
+                    int np,
                     double dt, double cb, double ca, double G, double e2, double e4,
                     const double *S, double *part, DevCounters *cnt, SlotStats *slots,
                     kep::KeplerParams kp, long long step, const kep::GuessNet &net)
@@ -922,7 +983,8 @@ void launch_pairs_h(int mode, int split, int ntiles, hipStream_t st, int n, int 
     // pairs it solves from the time it passes to the solver)
     const bool defkp = kp.tol == kep::DEFAULT_TOL && kp.max_iter == kep::DEFAULT_MAX_ITER;
     const bool halves = !HIST && defkp && cb == ca && ca == 0.5 * dt && dt != 0.0;
-#define SAKURA_TILE_ARGS split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, slots, \
+#define SAKURA_TILE_ARGS split, strips, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt, \
+                         slots, \
                          kp, step, net
     switch (mode) {
     case 1:
@@ -955,17 +1017,20 @@ void launch_pairs_h(int mode, int split, int ntiles, hipStream_t st, int n, int 
 #undef SAKURA_TILE_ARGS
 }
 
-void launch_pairs(bool hist, int mode, int split, int ntiles, hipStream_t st, int n, int nb, int np,
+void launch_pairs(bool hist, int mode, int split, StripLayout strips, int ntiles, hipStream_t st, int n,
+                  int nb, int np,
                   double dt, double cb, double ca, double G, double e2, double e4,
                   const double *S, double *part,
                   DevCounters *cnt, SlotStats *slots, kep::KeplerParams kp, long long step,
                   const kep::GuessNet &net)
 {
     if (hist)
-        launch_pairs_h<true>(mode, split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+        launch_pairs_h<true>(mode, split, strips, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S,
+                             part, cnt,
                              slots, kp, step, net);
     else
-        launch_pairs_h<false>(mode, split, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S, part, cnt,
+        launch_pairs_h<false>(mode, split, strips, ntiles, st, n, nb, np, dt, cb, ca, G, e2, e4, S,
+                              part, cnt,
                               slots, kp, step, net);
 }
 
@@ -1105,7 +1170,7 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     if (h->opts.kepler_rtol <= 0.0) h->opts.kepler_rtol = kep::DEFAULT_TOL;
     if (h->opts.max_iter <= 0) h->opts.max_iter = kep::DEFAULT_MAX_ITER;
     if (h->opts.max_iter > SAKURA_MAX_ITER || h->opts.tile_override < 0 ||
-        h->opts.tile_override > sk::TILE ||
+        h->opts.tile_override > sk::TILE || h->opts.row_strip < 0 || h->opts.row_strip > 64 ||
         (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED)) {
         delete h;
         return SAKURA_EINVAL;
@@ -1219,7 +1284,6 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
     double pair_ms = 0.0;
 
     const int ntiles = nb * (nb + 1) / 2;
-    const int split = pair_split(ntiles, h->cus);
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
     int mode = sk::guess_mode(h, &net);
@@ -1246,6 +1310,10 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
         net.defer_count = h->defer_idx;
         net.defer_tiles = h->defer_idx + ntiles;
     }
+    // a requested strip length runs one wavefront per tile; the pair launches
+    // and k_apply share the layout of the partial sums
+    const int split = h->opts.row_strip > 0 && mode != 2 ? 1 : pair_split(ntiles, h->cus);
+    const StripLayout strips = pair_strips(h->opts.row_strip, split, mode, nb, h->cus);
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
     sk::k_clear<<<1, sk::NSLOT, 0, st>>>(buf.cnt, buf.slots);
@@ -1257,11 +1325,12 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
             const size_t slot = timing ? (size_t)(e % ring) : 0;
             if (timing && e >= ring && (rc = read_pair_timing(h, slot, &pair_ms))) return rc;
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[2 + 2 * slot], st));
-            launch_pairs(h->opts.histogram != 0, mode, split, ntiles, st, (int)n, nb, np, g.t, g.cb,
-                         g.ca, G, e2, e4, buf.state, buf.part, buf.cnt, buf.slots, kp, s, net);
+            launch_pairs(h->opts.histogram != 0, mode, split, strips, ntiles, st, (int)n, nb, np,
+                         g.t, g.cb, g.ca, G, e2, e4, buf.state, buf.part, buf.cnt, buf.slots, kp,
+                         s, net);
             if (timing) SAKURA_HIP(h, hipEventRecord(h->events[3 + 2 * slot], st));
-            k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, g.after, g.next, buf.state,
-                                                 buf.part, buf.cnt, s);
+            k_apply<<<nb, 6 * sk::TILE, 0, st>>>((int)n, nb, np, strips, g.after, g.next,
+                                                 buf.state, buf.part, buf.cnt, s);
         }
     }
     k_export<<<(n + 255) / 256, 256, 0, st>>>((int)n, np, buf.state, r, v, buf.cnt);

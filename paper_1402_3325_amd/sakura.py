@@ -32,7 +32,7 @@ class SakuraError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("guess", ctypes.c_int), ("kepler_rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("histogram", ctypes.c_int),
-                ("tile_override", ctypes.c_int)]
+                ("tile_override", ctypes.c_int), ("row_strip", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -191,11 +191,13 @@ class Sakura:
     """A library handle bound to one GPU."""
 
     def __init__(self, device: int = 0, guess: int = GUESS_ANALYTIC, kepler_rtol: float = 0.0,
-                 max_iter: int = 0, histogram: bool = False, tile_override: int = 0):
+                 max_iter: int = 0, histogram: bool = False, tile_override: int = 0,
+                 row_strip: int = 0):
         self._lib = lib()
         self.device = device
         h = ctypes.c_void_p()
-        o = Opts(guess, kepler_rtol, max_iter, int(bool(histogram)), int(tile_override))
+        o = Opts(guess, kepler_rtol, max_iter, int(bool(histogram)), int(tile_override),
+                 int(row_strip))
         rc = self._lib.sakura_create(ctypes.byref(h), device, ctypes.byref(o))
         if rc != OK:
             raise SakuraError(rc, "sakura_create failed")

@@ -1,0 +1,101 @@
+"""The pair kernel's work items and k_apply's reduction order
+(paper_1402_3325_amd/csrc/tiles.hpp), built for the host: every unordered pair
+of blocks -- the tiles of the upper triangle, whose pairs make up the sum over
+all pairs of eq. (23) in Sec. 2.2 -- is covered by exactly one work item, and
+block K reduces exactly the partial-sum slots the items write for it, each
+once, in increasing slot order (no slot read that was not written in the same
+launch, none written and left out)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def lay(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("tiles") / "libtileshost.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                           os.path.join(HERE, "tiles_host_shim.cpp"), "-o", so])
+    L = ctypes.CDLL(so)
+    L.host_item_count.restype = ctypes.c_longlong
+    IP = ctypes.POINTER(ctypes.c_int)
+
+    def items(nb, S, kc):
+        n = L.host_item_count(nb, S, kc)
+        out = np.empty((n, 3), np.int32)
+        L.host_items(nb, S, kc, out.ctypes.data_as(IP))
+        return out
+
+    def slots(K, nb, S, kc):
+        out = np.empty(max(nb, 1), np.int32)
+        n = L.host_apply_slots(K, nb, S, kc, out.ctypes.data_as(IP))
+        return out[:n]
+    return items, slots
+
+
+def _check(lay, nb, S, kc):
+    items, slots = lay
+    it = items(nb, S, kc)
+    cover = np.zeros((nb, nb), np.int64)
+    written = np.zeros((nb, nb), np.int64)  # written[K, L]: writes to part[K][L]
+    for I, J0, ln in it:
+        assert 0 <= I <= J0 and ln >= 1 and J0 + ln <= nb, (nb, S, kc, I, J0, ln)
+        assert ln == 1 or (ln == S and I < kc)
+        for J in range(J0, J0 + ln):
+            cover[I, J] += 1
+            if J != I:
+                written[J, I] += 1  # j side of tile (I, J)
+        written[I, J0] += 1  # the item's i side
+    assert np.array_equal(cover, np.triu(np.ones((nb, nb), np.int64))), (nb, S, kc)
+    for K in range(nb):
+        sl = slots(K, nb, S, kc)
+        assert np.all(np.diff(sl) > 0)
+        assert np.array_equal(sl, np.flatnonzero(written[K])), (nb, S, kc, K)
+        assert written[K].max() == 1
+    return it
+
+
+@pytest.mark.parametrize("S", [1, 2, 3, 4, 8, 64])
+def test_items_cover_every_tile_once(lay, S):
+    for nb in list(range(1, 34)) + [63, 64, 65, 100, 129]:
+        for kc in sorted({0, 1, nb // 3, nb // 2, nb - 1, nb} - {-1}):
+            _check(lay, nb, S, kc)
+
+
+def test_one_tile_per_item_is_the_plain_order(lay):
+    """S = 1 (or no strip rows): off-diagonal tiles column by column, then the
+    diagonal, and k_apply reads the slots L = 0..nb-1."""
+    items, slots = lay
+    nb = 23
+    want = [(i, j, 1) for j in range(nb) for i in range(j)] + [(k, k, 1) for k in range(nb)]
+    for S, kc in ((1, nb), (4, 0)):
+        assert [tuple(r) for r in items(nb, S, kc)] == want
+        for K in range(nb):
+            assert list(slots(K, nb, S, kc)) == list(range(nb))
+
+
+@pytest.mark.parametrize("kc", [256, 165])
+def test_strips_first_single_tiles_last(lay, kc):
+    """Strips of S tiles come before the single tiles; the rows of single tiles
+    only end the launch, their diagonal tiles last."""
+    items, slots = lay
+    nb, S = 256, 4
+    it = items(nb, S, kc)
+    lens = it[:, 2]
+    ns = int(np.sum(lens == S))
+    assert np.all(lens[:ns] == S) and np.all(lens[ns:] == 1)
+    diag = np.flatnonzero(it[:, 0] == it[:, 1])
+    tail = len(it) - (nb - kc)
+    if kc < nb:
+        assert np.array_equal(np.flatnonzero((it[:, 0] == it[:, 1]) & (it[:, 0] >= kc)),
+                              np.arange(tail, len(it)))
+    assert len(diag) == nb
+    # partial sums written and read, in blocks of 64 x 6 doubles: one j side per
+    # off-diagonal tile, one i side per item (nb^2 = 65536 with one tile per item)
+    blocks = sum(len(slots(K, nb, S, kc)) for K in range(nb))
+    assert blocks == nb * (nb - 1) // 2 + len(it)
+    assert blocks == {256: 41152, 165: 44188}[kc]
