@@ -72,15 +72,16 @@ typedef struct {
                            64-lane tile is one wavefront per system).  The single-system
                            pair kernel has one tile, 64 x 64 particles (the wavefront
                            width), and ignores it.  EINVAL outside [0, 64]. */
-    int row_strip;      /* single-system pair kernel (Sec. 2.2, the sum over pairs of eq. 23):
-                           tiles per work item along a row of the upper triangle of 64 x 64
-                           tiles, whose i-side partial sums are written once per item.  0
-                           picks strips of 4 tiles in the rows before a last triangle of at
-                           least two tiles per wavefront slot, whose rows stay single tiles
-                           (none where a small system's tiles are split over wavefronts);
-                           S >= 1 asks for S in every row, one wavefront per tile (S is
-                           capped at the number of 64-particle blocks; the learned starter's
-                           deferred pairs take 1).
+    int row_strip;      /* single-system pair kernel of the plain starter (Sec. 2.2, the sum
+                           over pairs of eq. 23): tiles per work item along a row of the upper
+                           triangle of 64 x 64 tiles, whose i-side partial sums are written
+                           once per item.  0 picks strips of 4 tiles in the rows before a
+                           last triangle of at least two tiles per wavefront slot, whose rows
+                           stay single tiles (none where a small system's tiles are split
+                           over wavefronts); S >= 1 asks for S in every row, with one
+                           wavefront per tile (S is capped at the number of 64-particle
+                           blocks).  The close-pair hybrid, a loaded starter network and the
+                           harvest of training rows take one tile per item.
                            The partial sums are added in another grouping for each S, so the
                            results agree to rounding, not bit for bit, across S.  EINVAL
                            outside [0, 64]. */

@@ -220,17 +220,23 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
         if (s_stop) return;
     }
     // the work item: tiles (I, J0), ..., (I, J0 + len - 1).  Strips of several
-    // tiles need SPLIT 1 (with SPLIT > 1 the wavefronts combine their i-side
-    // sums in LDS per tile) and a mode other than 4 (whose deferred-pair list
-    // belongs to one tile).
-    int I, J0, len;
-    layout_item(blockIdx.x, nb, (SPLIT == 1 && MODE != 4) ? strips : StripLayout{1, 0}, I, J0,
-                len);
-    // uniform: the decoding's divisions and square root run on the vector ALU,
-    // and values left there would keep the sub-step counter there too
-    I = __builtin_amdgcn_readfirstlane(I);
-    J0 = __builtin_amdgcn_readfirstlane(J0);
-    len = __builtin_amdgcn_readfirstlane(len);
+    // tiles are built into the plain modes' kernels of one wavefront per tile
+    // only: with SPLIT > 1 the wavefronts combine their i-side sums in LDS per
+    // tile, mode 4's deferred-pair list belongs to one tile, and the loop over
+    // a strip's tiles costs the other modes' kernels, which hold more state,
+    // registers they do not have (the hybrid's spilled).
+    constexpr bool STRIPS = SPLIT == 1 && MODE == 0;
+    int I, J0, len = 1;
+    if constexpr (STRIPS) {
+        layout_item(blockIdx.x, nb, strips, I, J0, len);
+        // uniform: the decoding's divisions and square root run on the vector
+        // ALU, and values left there would keep the sub-step counter there too
+        I = __builtin_amdgcn_readfirstlane(I);
+        J0 = __builtin_amdgcn_readfirstlane(J0);
+        len = __builtin_amdgcn_readfirstlane(len);
+    } else {
+        tile_blocks(blockIdx.x, nb, I, J0);
+    }
     static_assert(SPLIT == 1 || MODE != 4, "the deferred-pair list is one wavefront's");
     const int lane = SPLIT == 1 ? (int)threadIdx.x : (int)threadIdx.x % TILE;
     const int wv = SPLIT == 1 ? 0 : (int)threadIdx.x / TILE;
@@ -932,12 +938,12 @@ int pair_split(int ntiles, int cus)
 // tiles per wavefront slot, stay single tiles, which the launch ends with,
 // and the rows before them are strips of 4 tiles (a strip then takes about
 // half of the launch at N = 16384; with 8 tiles, as long as the launch, the
-// launch took 10 % longer).  A requested S puts strips of S in every row.  Strips need
-// SPLIT 1 and a mode other than the deferred-pair list's (mode 2 here, 4 in
-// the kernel).
+// launch took 10 % longer).  A requested S puts strips of S in every row.
+// Strips are built into the plain starter's kernels of one wavefront per tile
+// only (mode 0, SPLIT 1).
 StripLayout pair_strips(int requested, int split, int mode, int nb, int cus)
 {
-    if (split > 1 || mode == 2) return StripLayout{1, 0};
+    if (split > 1 || mode != 0) return StripLayout{1, 0};
     if (requested > 0) return StripLayout{std::min(requested, std::max(nb, 1)), nb};
     const int64_t tail = 2 * (int64_t)cus * 16; // wavefront slots: 4 SIMDs x 4 wavefronts per CU
     int64_t nt = 0;
