@@ -3,12 +3,14 @@
 Each row of eqs. (27b, 27c) sums N - 1 weighted pair increments.  The tile
 kernel adds them in chains of at most 64 terms (one 64 x 64 tile: the i-side
 sums in registers, the j-side sums in LDS, both one fused multiply-add per
-term), and combines the nb tile partials of a row with TwoSum in a fixed
-order.  A chain of k rounded additions errs by at most gamma_k = k u / (1 - k u)
-times the sum of the magnitudes it adds (u = 2^-53), and the compensated
-combination by 2 u |S| plus terms of order nb^2 u^2, so a row's summation
-error is below gamma_64 sum_j |t_j| + 2 u |S|, against gamma_(N-1) sum_j |t_j|
-for one flat chain of N - 1 terms.
+term); where a work item is a row strip of up to 4 tiles, the strip adds its
+tiles' i-side chain results in one more chain of at most 3 additions; and the
+partials of a row are combined with TwoSum in a fixed order.  A chain of k
+rounded additions errs by at most gamma_k = k u / (1 - k u) times the sum of
+the magnitudes it adds (u = 2^-53), and nested chains by gamma of their total
+depth; the compensated combination adds 2 u |S| plus terms of order nb^2 u^2,
+so a row's summation error is below gamma_67 sum_j |t_j| + 2 u |S|, against
+gamma_(N-1) sum_j |t_j| for one flat chain of N - 1 terms.
 
 The first test evaluates both bounds on the benchmark cluster (N = 16384) from
 the oracle's own increments, for the central mass, the members of the
@@ -47,7 +49,7 @@ def test_blocked_bound_holds_on_the_benchmark_cluster(oracle):
                          (dv, max(np.linalg.norm(v[i]), v_rms))):
             A = np.abs(t).sum(0)
             S = np.abs(t.sum(0))
-            blocked = float(np.max(gamma(64) * A + 2.0 * U * S)) / scale
+            blocked = float(np.max(gamma(64 + 3) * A + 2.0 * U * S)) / scale
             flat = float(np.max(gamma(n - 1) * A)) / scale
             worst_blocked = max(worst_blocked, blocked)
             worst_flat = max(worst_flat, flat)
@@ -57,14 +59,22 @@ def test_blocked_bound_holds_on_the_benchmark_cluster(oracle):
     assert worst_flat > 1e-12  # a flat chain would not be guaranteed
 
 
-def _kernel_order_sum(t, tile=64):
+def _kernel_order_sum(t, tile=64, strip=1):
     """The tile kernel's order on one row's terms: chains of `tile` rounded
-    additions, then TwoSum over the chain results in order, and s + e."""
-    parts = []
+    additions; the chain results of `strip` consecutive tiles added in one
+    more chain (a row strip's i side); then TwoSum over those in order, and
+    s + e."""
+    chains = []
     for a in range(0, len(t), tile):
         acc = 0.0
         for x in t[a:a + tile]:
             acc = acc + float(x)
+        chains.append(acc)
+    parts = []
+    for a in range(0, len(chains), strip):
+        acc = chains[a]
+        for x in chains[a + 1:a + strip]:
+            acc = acc + x
         parts.append(acc)
     s = e = 0.0
     for x in parts:
@@ -95,8 +105,10 @@ def test_blocked_order_holds_where_a_flat_chain_fails():
     exact = math.fsum(t.tolist())
     scale = 0.5 * A  # a velocity scale of the order of the large increment
     e_flat = abs(_flat_sum(t) - exact) / scale
-    e_blocked = abs(_kernel_order_sum(t) - exact) / scale
-    print(f"constructed worst case: flat {e_flat:.2e}, kernel order {e_blocked:.2e}")
     assert e_flat > 1e-12
-    assert e_blocked <= 2.0 * gamma(64) * (2 * A) / scale
-    assert e_blocked <= 1e-13
+    for strip in (1, 4):
+        e_blocked = abs(_kernel_order_sum(t, strip=strip) - exact) / scale
+        print(f"constructed worst case: flat {e_flat:.2e}, kernel order with strips of "
+              f"{strip}: {e_blocked:.2e}")
+        assert e_blocked <= 2.0 * gamma(64 + strip - 1) * (2 * A) / scale
+        assert e_blocked <= 1e-13
