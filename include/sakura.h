@@ -78,13 +78,16 @@ typedef struct {
                            once per item.  0 picks strips of 4 tiles in the rows before a
                            last triangle of at least two tiles per wavefront slot, whose rows
                            stay single tiles (none where a small system's tiles are split
-                           over wavefronts); S >= 1 asks for S in every row, with one
-                           wavefront per tile (S is capped at the number of 64-particle
-                           blocks).  The close-pair hybrid, a loaded starter network and the
-                           harvest of training rows take one tile per item.
+                           over wavefronts); S = 1, 2, 4, ..., 64 asks for S in every row,
+                           with one wavefront per tile (S is capped at the number of
+                           64-particle blocks).  The close-pair hybrid, a loaded starter
+                           network and the harvest of training rows take one tile per item.
+                           The partial sums are stored compactly, one block of 64 x 6 doubles
+                           per slot k_apply reads: nb^2 blocks with one tile per item (nb the
+                           number of 64-particle blocks), 0.72 nb^2 at nb = 256 by default.
                            The partial sums are added in another grouping for each S, so the
                            results agree to rounding, not bit for bit, across S.  EINVAL
-                           outside [0, 64]. */
+                           for S outside [0, 64] or not a power of two. */
 } sakura_opts;
 
 typedef struct {

@@ -232,12 +232,19 @@ int grow(sakura_t *h, T **buf, int64_t *cap, int64_t need)
 // The single-system path keeps 10 np doubles of state and nb^2 blocks of
 // 6 x 64 doubles of partial sums (np = 64 nb >= n); n whose buffers exceed the
 // device's memory (or the 2^21 of the tile grid's int indexing) is EINVAL.
-inline int check_capacity(sakura_t *h, int64_t n)
+inline int check_size(sakura_t *h, int64_t n)
 {
-    const int64_t nb = (n + TILE - 1) / TILE;
     if (n > ((int64_t)1 << 21))
         return fail(h, SAKURA_EINVAL, "n = " + std::to_string(n) + " exceeds 2^21");
-    const double need = (double)nb * (double)nb * 6.0 * TILE * 8.0 + 10.0 * nb * TILE * 8.0;
+    return SAKURA_OK;
+}
+
+// The partial sums (part_doubles) and the state of n particles must fit the
+// device's memory.
+inline int check_capacity(sakura_t *h, int64_t n, int64_t part_doubles)
+{
+    const int64_t nb = (n + TILE - 1) / TILE;
+    const double need = (double)part_doubles * 8.0 + 10.0 * nb * TILE * 8.0;
     size_t total = 0;
     if (hipDeviceTotalMem(&total, h->device) != hipSuccess) total = 0;
     if (total && need > (double)total)

@@ -3,9 +3,12 @@
 // Data layout in HBM (library-owned, per handle):
 //   state[10][np] float64 structure-of-arrays, np = 64 * ceil(n / 64):
 //     row 0 m, rows 1-3 r (after the step), rows 4-6 v, rows 7-9 r half-drifted
-//   part[nb][nb][6][64] float64: part[K][L][c][l] = sum over the 64 particles of
-//     block L of the weighted increment component c (dr xyz, dv xyz) received by
-//     particle 64 K + l from pairs with block L (the diagonal block for L = K).
+//   partial sums, float64 blocks [6][64]: slot k of block K holds, for
+//     component c (dr xyz, dv xyz) and particle 64 K + l, the sum of the
+//     weighted increments it receives from one tile's or one row strip's pairs
+//     (tiles.hpp: slots k < K the j sides of tiles (k, K), then the i sides of
+//     row K's work items); block K's slots follow one another from
+//     apply_offset(K), nb^2 slots with one tile per work item.
 // Per step: k_pairs (eqs. 26, 23 over all unordered pairs) then k_apply
 // (eqs. 27b-d and the next step's 27a); a composition of the step (Sec. 2.2)
 // runs one such pair of launches per stage.  k_import / k_export convert
@@ -170,8 +173,8 @@ __device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, 
 // in registers and rotated by one lane per sub-step instead, they cost twelve
 // DPP moves per pair on the vector ALU, which bounds this kernel.)  The
 // diagonal tile runs s = 1..32 (s = 32 on half the lanes), which visits each
-// pair i < j once.  Partial sums go to part[I][J] (i side) and part[J][I]
-// (j side).
+// pair i < j once.  Partial sums go to slot I of block J (j side) and to
+// the work item's slot of block I (i side).
 // The pair map is the back-drift cb of the relative position, the Kepler flow
 // over tau and the back-drift ca (eq. 26: cb = ca = tau/2; eq. 19b: cb = tau,
 // ca = 0; eq. 19a: cb = 0, ca = tau), with tau = cb + ca, which every
@@ -226,6 +229,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     // a strip's tiles costs the other modes' kernels, which hold more state,
     // registers they do not have (the hybrid's spilled).
     constexpr bool STRIPS = SPLIT == 1 && MODE == 0;
+    const StripLayout lay = STRIPS ? strips : StripLayout{1, 0}; // of the partial sums
     int I, J0, len = 1;
     if constexpr (STRIPS) {
         layout_item(blockIdx.x, nb, strips, I, J0, len);
@@ -286,6 +290,10 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
     double tau_v = tau;
     asm volatile("" : "+v"(tau_v));
 
+    // the partial-sum slots (tiles.hpp; fewer than 2^31): the item's i side in
+    // block I, and the first slot of the current tile's block J
+    const int slot_i = (int)(apply_offset(I, nb, lay) + item_slot(I, J0, nb, lay));
+    int slot_j = (int)apply_offset(J0, nb, lay);
     for (int J = J0; J < J0 + len; ++J) {
         const bool diag = (I == J);
         const int jg = J * TILE + lane;
@@ -543,14 +551,15 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
                 }
             }
             const size_t cs = TILE; // component stride inside a partial
+            // slot I of block J (the j side)
             if (!diag) {
-                double *pji = part + ((size_t)J * nb + I) * 6 * cs + lane;
+                double *pji = part + (size_t)(slot_j + I) * 6 * cs + lane;
                 for (int c = 0; c < 6; ++c) pji[c * cs] = aj[c];
             }
             // the tile's i side (on the diagonal both sides are block I's): an item
             // of one tile writes it; a strip adds it to its earlier tiles' sums, in
             // tile order, and writes the total after its last tile
-            double *pij = part + ((size_t)I * nb + J0) * 6 * cs + lane;
+            double *pij = part + (size_t)slot_i * 6 * cs + lane;
             for (int c = 0; c < 6; ++c) {
                 const double o = diag ? ai[c] + aj[c] : ai[c];
                 if (len == 1) {
@@ -562,6 +571,7 @@ __global__ __launch_bounds__(TILE * SPLIT, 4) void k_pairs(int n, int nb, int np
                 }
             }
         }
+        slot_j += apply_slots(J, nb, lay); // block J + 1 starts after block J's slots
         // with SPLIT each wavefront counts the sub-steps it took
         nsub_w += SPLIT == 1 ? s1 - s0 : (s1 - s0 - wv + SPLIT - 1) / SPLIT;
     } // tiles of the item
@@ -664,7 +674,9 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
         sidx[lane][1] = j - J * TILE;
         __syncthreads();
         // list order: lane c < 6 adds component c of every listed pair, i side to
-        // part[I][J], j side to part[J][I] (no two lanes touch one address)
+        // slot J of block I, j side to slot I of block J (the listing kernel runs
+        // one tile per work item: block K's slots are its tiles' columns, nb per
+        // block; no two lanes touch one address)
         if (lane < 6) {
             double *pi = part + (((size_t)I * nb + J) * 6 + lane) * TILE;
             double *pj = part + (((size_t)J * nb + I) * 6 + lane) * TILE;
@@ -695,17 +707,17 @@ __global__ __launch_bounds__(TILE) void k_deferred(int nb, int np, double tau, d
     }
 }
 
-// TwoSum of the partial-sum slots k0.. of one component into (s, e), in slot
-// order, B loads in flight per round.
+// TwoSum of the nslot partial-sum slots of one component (stride apart) into
+// (s, e), in slot order, B loads in flight per round.
 template <int B>
-__device__ inline void reduce_slots(const double *__restrict__ p, size_t stride, int nslot, int K,
-                                    int nb, StripLayout strips, double &s, double &e)
+__device__ inline void reduce_slots(const double *__restrict__ p, size_t stride, int nslot,
+                                    double &s, double &e)
 {
     int k0 = 0;
     for (; k0 + B <= nslot; k0 += B) {
         double x[B];
 #pragma unroll
-        for (int k = 0; k < B; ++k) x[k] = p[(size_t)apply_slot(k0 + k, K, nb, strips) * stride];
+        for (int k = 0; k < B; ++k) x[k] = p[(size_t)(k0 + k) * stride];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const double t = s + x[k];
@@ -715,7 +727,7 @@ __device__ inline void reduce_slots(const double *__restrict__ p, size_t stride,
         }
     }
     for (; k0 < nslot; ++k0) {
-        const double x = p[(size_t)apply_slot(k0, K, nb, strips) * stride];
+        const double x = p[(size_t)k0 * stride];
         const double t = s + x;
         const double bp = t - s;
         e += (s - (t - bp)) + (x - bp);
@@ -744,7 +756,8 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, Strip
         cnt->defer_next = 0;
     }
     __shared__ double dsum[6][TILE];
-    const double *p = part + ((size_t)K * nb * 6 + c) * TILE + lane;
+    // block K's slots, stored one after the other in reduction order
+    const double *p = part + ((size_t)apply_offset(K, nb, strips) * 6 + c) * TILE + lane;
     const size_t stride = 6 * TILE;
     double s = 0.0, e = 0.0;
     const int nslot = apply_slots(K, nb, strips);
@@ -752,8 +765,8 @@ __global__ __launch_bounds__(6 * TILE) void k_apply(int n, int nb, int np, Strip
     // the single-tile rows, which set the launch's length: 16 loads in flight
     // shorten them (with every block reading nb slots the launch is bound by
     // the memory, and 8 do better).
-    if (strips_on(strips)) reduce_slots<16>(p, stride, nslot, K, nb, strips, s, e);
-    else reduce_slots<8>(p, stride, nslot, K, nb, strips, s, e);
+    if (strips_on(strips)) reduce_slots<16>(p, stride, nslot, s, e);
+    else reduce_slots<8>(p, stride, nslot, s, e);
     dsum[c][lane] = s + e;
     __syncthreads();
     if (c != 0) return;
@@ -928,27 +941,6 @@ int pair_split(int ntiles, int cus)
     int split = 1;
     while (split < 4 && (int64_t)ntiles * split < 2 * slots) split *= 2;
     return split;
-}
-
-// The work items of the pair launch for the plain kernel of one wavefront
-// per tile.  Strips of S tiles along a row write one i-side partial per strip
-// instead of one per tile (and start a wavefront once per strip), but a
-// launch cannot end before its longest item, and long items drain it
-// unevenly.  So the rows of the last blocks, a triangle of at least two
-// tiles per wavefront slot, stay single tiles, which the launch ends with,
-// and the rows before them are strips of 4 tiles (a strip then takes about
-// half of the launch at N = 16384; with 8 tiles, as long as the launch, the
-// launch took 10 % longer).  A requested S puts strips of S in every row.
-// Strips are built into the plain starter's kernels of one wavefront per tile
-// only (mode 0, SPLIT 1).
-StripLayout pair_strips(int requested, int split, int mode, int nb, int cus)
-{
-    if (split > 1 || mode != 0) return StripLayout{1, 0};
-    if (requested > 0) return StripLayout{std::min(requested, std::max(nb, 1)), nb};
-    const int64_t tail = 2 * (int64_t)cus * 16; // wavefront slots: 4 SIMDs x 4 wavefronts per CU
-    int64_t nt = 0;
-    while (nt < nb && nt * (nt + 1) / 2 < tail) ++nt;
-    return StripLayout{4, (int)(nb - nt)};
 }
 
 // One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one),
@@ -1177,6 +1169,7 @@ int sakura_create(sakura_t **out, int device, const sakura_opts *opts)
     if (h->opts.max_iter <= 0) h->opts.max_iter = kep::DEFAULT_MAX_ITER;
     if (h->opts.max_iter > SAKURA_MAX_ITER || h->opts.tile_override < 0 ||
         h->opts.tile_override > sk::TILE || h->opts.row_strip < 0 || h->opts.row_strip > 64 ||
+        (h->opts.row_strip & (h->opts.row_strip - 1)) != 0 ||
         (h->opts.guess != SAKURA_GUESS_ANALYTIC && h->opts.guess != SAKURA_GUESS_LEARNED)) {
         delete h;
         return SAKURA_EINVAL;
@@ -1259,7 +1252,7 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
     if (!std::isfinite(dt) || !std::isfinite(G) || !(G > 0.0))
         return sk::fail(h, SAKURA_EINVAL, "dt and G must be finite and G > 0");
     int rc;
-    if (!buf.fixed && (rc = sk::check_capacity(h, n))) return rc;
+    if (!buf.fixed && (rc = sk::check_size(h, n))) return rc;
     if (nsteps < 0) return sk::fail(h, SAKURA_EINVAL, "nsteps < 0");
     Stage stages[3];
     int nstage = 0;
@@ -1272,23 +1265,6 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
     hipStream_t st = (hipStream_t)stream;
     const int nb = (int)((n + sk::TILE - 1) / sk::TILE);
     const int np = nb * sk::TILE;
-    if (!buf.fixed) {
-        if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
-        if ((rc = sk::grow(h, &h->part, &h->cap_part, (int64_t)nb * nb * 6 * sk::TILE)))
-            return rc;
-        buf.state = h->state;
-        buf.part = h->part;
-    }
-    // the allocation-free path creates no events: it reports no timings
-    const bool timing = stats != nullptr && !buf.fixed;
-    const int64_t nlaunch = nsteps * nstage;
-    // pair launches are timed with a ring of event pairs: a pair is read back
-    // (waiting for the launch it bracketed) before it is recorded again, so a
-    // long evolve holds at most TIMING_RING launches' events
-    const int64_t ring = std::min<int64_t>(nlaunch, TIMING_RING);
-    if (timing && (rc = need_events(h, 2 + 2 * (size_t)ring))) return rc;
-    double pair_ms = 0.0;
-
     const int ntiles = nb * (nb + 1) / 2;
     const kep::KeplerParams kp{h->opts.kepler_rtol, h->opts.max_iter};
     kep::GuessNet net{};
@@ -1308,6 +1284,31 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
         return sk::fail(h, SAKURA_EINVAL,
                         "the allocation-free entry point runs the plain starter only "
                         "(no learned starter, no harvest)");
+    // a requested strip length runs one wavefront per tile; the pair launches
+    // and k_apply share the layout of the partial sums, stored compactly
+    const int split = h->opts.row_strip > 0 && mode == 0 ? 1 : pair_split(ntiles, h->cus);
+    // wavefront slots: 4 SIMDs x 4 wavefronts per CU
+    const StripLayout strips =
+        choose_strips(h->opts.row_strip, split == 1 && mode == 0, nb, 16 * (long long)h->cus);
+    if (strips.S < 1 || (strips.S & (strips.S - 1)) != 0 || strips.kc < 0 || strips.kc > nb)
+        return sk::fail(h, SAKURA_EINVAL, "internal: strip layout out of range");
+    const int64_t part_doubles = apply_offset(nb, nb, strips) * 6 * sk::TILE;
+    if (!buf.fixed) {
+        if ((rc = sk::check_capacity(h, n, part_doubles))) return rc;
+        if ((rc = sk::grow(h, &h->state, &h->cap_np, 10 * (int64_t)np))) return rc;
+        if ((rc = sk::grow(h, &h->part, &h->cap_part, part_doubles))) return rc;
+        buf.state = h->state;
+        buf.part = h->part;
+    }
+    // the allocation-free path creates no events: it reports no timings
+    const bool timing = stats != nullptr && !buf.fixed;
+    const int64_t nlaunch = nsteps * nstage;
+    // pair launches are timed with a ring of event pairs: a pair is read back
+    // (waiting for the launch it bracketed) before it is recorded again, so a
+    // long evolve holds at most TIMING_RING launches' events
+    const int64_t ring = std::min<int64_t>(nlaunch, TIMING_RING);
+    if (timing && (rc = need_events(h, 2 + 2 * (size_t)ring))) return rc;
+    double pair_ms = 0.0;
     if (mode == 2) { // lists of deferred pairs
         if ((rc = sk::grow(h, &h->defer_pairs, &h->cap_defer, (int64_t)ntiles * kep::DEFER_CAP)))
             return rc;
@@ -1316,10 +1317,6 @@ int evolve_run(sakura_t *h, int64_t n, const double *m, double *r, double *v, do
         net.defer_count = h->defer_idx;
         net.defer_tiles = h->defer_idx + ntiles;
     }
-    // a requested strip length runs one wavefront per tile; the pair launches
-    // and k_apply share the layout of the partial sums
-    const int split = h->opts.row_strip > 0 && mode != 2 ? 1 : pair_split(ntiles, h->cus);
-    const StripLayout strips = pair_strips(h->opts.row_strip, split, mode, nb, h->cus);
 
     if (timing) SAKURA_HIP(h, hipEventRecord(h->events[0], st));
     sk::k_clear<<<1, sk::NSLOT, 0, st>>>(buf.cnt, buf.slots);

@@ -127,9 +127,10 @@ def test_parity_split_tiles(torch, lib, oracle, n):
 @pytest.mark.parametrize("n", [1000, 3000])
 def test_parity_row_strips(torch, oracle, n):
     """Work items of S tiles along a row of the upper triangle (opts.row_strip,
-    one wavefront per tile), the i-side partial sums written once per item:
-    S = 2, 3, 8 and S past the number of blocks (every row one strip, the
-    diagonal tile first), on 16 and 47 blocks with a ragged last block.  Every
+    one wavefront per tile), the i-side partial sums written once per item and
+    stored compactly: S = 2, 4, 8 and S past the number of blocks (every row
+    one strip, the diagonal tile first), on 16 and 47 blocks with a ragged last
+    block.  Every
     row against the oracle; the exact pair-solve count; the results of
     different S within rounding of each other (the partial sums are grouped
     differently); the diagnostic copy with the same S bitwise equal."""
@@ -137,7 +138,7 @@ def test_parity_row_strips(torch, oracle, n):
     m, r, v, tau = workloads.cluster(n_stars=n - 1, rng=np.random.default_rng(7100 + n))
     ro, vo = oracle.step(m, r, v, tau)
     outs = {}
-    for S in (1, 2, 3, 8, 64):
+    for S in (1, 2, 4, 8, 64):
         h = Sakura(0, row_strip=S)
         try:
             rg, vg, st = gpu_step(torch, h, m, r, v, tau, stats=True)
@@ -148,16 +149,16 @@ def test_parity_row_strips(torch, oracle, n):
         assert er <= TOL and ev <= TOL, (S, er, ev)
         assert st["pair_solves"] == n * (n - 1) // 2
         outs[S] = (rg, vg, st)
-    for S in (2, 3, 8, 64):
+    for S in (2, 4, 8, 64):
         e = step_error(outs[S][0], outs[S][1], outs[1][0], outs[1][1], r, v)
         assert max(e) <= 1e-14, (S, e)
         assert outs[S][2]["iters_total"] == outs[1][2]["iters_total"]
-    hd = Sakura(0, histogram=True, row_strip=3)
+    hd = Sakura(0, histogram=True, row_strip=4)
     try:
         rd, vd, sd = gpu_step(torch, hd, m, r, v, tau, stats=True)
     finally:
         hd.close()
-    assert np.array_equal(rd, outs[3][0]) and np.array_equal(vd, outs[3][1])
+    assert np.array_equal(rd, outs[4][0]) and np.array_equal(vd, outs[4][1])
     assert sd["pair_solves"] == int(np.sum(sd["hist"]))
 
 
@@ -219,12 +220,13 @@ def test_boundary_rejects_invalid_arguments(torch, lib):
         with pytest.raises(SakuraError) as e:
             Sakura(0, tile_override=bad)
         assert e.value.code == EINVAL
+    for bad in (-1, 3, 65, 128):
         with pytest.raises(SakuraError) as e:
             Sakura(0, row_strip=bad)
         assert e.value.code == EINVAL
     blob = (ctypes.c_char * 64)()
     assert lib._lib.sakura_set_guess_model(lib._h, ctypes.cast(blob, ctypes.c_void_p), 64) == EINVAL
-    # 2^20 particles would need 0.8 TB of partial sums
+    # 2^20 particles would need 0.5 TB of partial sums (0.8 TB with one tile per item)
     n = 1 << 20
     mb = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
     rb = torch.rand((n, 3), dtype=torch.float64, device="cuda")

@@ -4,7 +4,8 @@ of blocks -- the tiles of the upper triangle, whose pairs make up the sum over
 all pairs of eq. (23) in Sec. 2.2 -- is covered by exactly one work item, and
 block K reduces exactly the partial-sum slots the items write for it, each
 once, in increasing slot order (no slot read that was not written in the same
-launch, none written and left out)."""
+launch, none written and left out), and the compact storage of those slots
+holds each at the place k_apply reads it from."""
 import ctypes
 import os
 import subprocess
@@ -34,6 +35,19 @@ def lay(tmp_path_factory):
         out = np.empty(max(nb, 1), np.int32)
         n = L.host_apply_slots(K, nb, S, kc, out.ctypes.data_as(IP))
         return out[:n]
+    L.host_choose_strips.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_longlong, IP]
+
+    def choose(requested, plain, nb, slots):
+        out = np.zeros(2, np.int32)
+        L.host_choose_strips(requested, int(plain), nb, slots, out.ctypes.data_as(IP))
+        return int(out[0]), int(out[1])
+    items.choose = choose
+    L.host_apply_offset.restype = ctypes.c_longlong
+    L.host_apply_offset.argtypes = [ctypes.c_int] * 4
+    L.host_item_slot.argtypes = [ctypes.c_int] * 5
+    slots.offset = L.host_apply_offset
+    slots.item_slot = L.host_item_slot
     return items, slots
 
 
@@ -51,15 +65,28 @@ def _check(lay, nb, S, kc):
                 written[J, I] += 1  # j side of tile (I, J)
         written[I, J0] += 1  # the item's i side
     assert np.array_equal(cover, np.triu(np.ones((nb, nb), np.int64))), (nb, S, kc)
+    lists = []
     for K in range(nb):
         sl = slots(K, nb, S, kc)
         assert np.all(np.diff(sl) > 0)
         assert np.array_equal(sl, np.flatnonzero(written[K])), (nb, S, kc, K)
         assert written[K].max() == 1
+        lists.append(sl)
+    # compact storage: block K's slots one after the other from apply_offset(K),
+    # the item's i side at the place of its first tile's column in block I's list,
+    # the j side of tile (I, J) at place I of block J's
+    assert slots.offset(0, nb, S, kc) == 0
+    for K in range(nb):
+        assert slots.offset(K + 1, nb, S, kc) - slots.offset(K, nb, S, kc) == len(lists[K])
+    for I, J0, ln in it:
+        k = slots.item_slot(I, J0, nb, S, kc)
+        assert lists[I][k] == J0, (nb, S, kc, I, J0)
+        for J in range(J0 + (J0 == I), J0 + ln):
+            assert lists[J][I] == I
     return it
 
 
-@pytest.mark.parametrize("S", [1, 2, 3, 4, 8, 64])
+@pytest.mark.parametrize("S", [1, 2, 4, 8, 16, 64])
 def test_items_cover_every_tile_once(lay, S):
     for nb in list(range(1, 34)) + [63, 64, 65, 100, 129]:
         for kc in sorted({0, 1, nb // 3, nb // 2, nb - 1, nb} - {-1}):
@@ -97,5 +124,29 @@ def test_strips_first_single_tiles_last(lay, kc):
     # partial sums written and read, in blocks of 64 x 6 doubles: one j side per
     # off-diagonal tile, one i side per item (nb^2 = 65536 with one tile per item)
     blocks = sum(len(slots(K, nb, S, kc)) for K in range(nb))
-    assert blocks == nb * (nb - 1) // 2 + len(it)
+    assert blocks == nb * (nb - 1) // 2 + len(it) == slots.offset(nb, nb, S, kc)
     assert blocks == {256: 41152, 165: 44188}[kc]
+
+
+def test_chosen_layouts_are_valid(lay):
+    """The layout the library picks for every block count and request: a strip
+    length that is a power of two (the layout's arithmetic divides by it with
+    shifts), a requested one at most nb (a request past nb is cut to the
+    largest power of two below it: 64 on 47 blocks gives 32, never 47), strip
+    rows within [0, nb]; and each such layout covers every tile once."""
+    items, slots = lay
+    for nb in range(1, 300):
+        for req in (0, 1, 2, 4, 8, 16, 32, 64):
+            for plain in (True, False):
+                S, kc = items.choose(req, plain, nb, 4096)
+                assert S >= 1 and S & (S - 1) == 0 and 0 <= kc <= nb, (nb, req, S, kc)
+                if not plain:
+                    assert (S, kc) == (1, 0)
+                elif req:
+                    assert kc == nb and S == min(req, 1 << (nb.bit_length() - 1))
+    assert items.choose(64, True, 47, 4096) == (32, 47)
+    assert items.choose(0, True, 256, 4096) == (4, 128)
+    for nb in (1, 5, 16, 47, 130, 200):
+        for req in (0, 4, 64):
+            S, kc = items.choose(req, True, nb, 64)
+            _check(lay, nb, S, kc)

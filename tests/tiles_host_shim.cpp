@@ -30,3 +30,23 @@ extern "C" int host_apply_slots(int K, int nb, int S, int kc, int *out)
     for (int k = 0; k < n; ++k) out[k] = sk::apply_slot(k, K, nb, L);
     return n;
 }
+
+// Start of block K's slots in the compact storage, K = 0..nb (nb: the whole buffer).
+extern "C" long long host_apply_offset(int K, int nb, int S, int kc)
+{
+    return sk::apply_offset(K, nb, sk::StripLayout{S, kc});
+}
+
+extern "C" int host_item_slot(int I, int J0, int nb, int S, int kc)
+{
+    return sk::item_slot(I, J0, nb, sk::StripLayout{S, kc});
+}
+
+// The layout the library picks: out[0] = S, out[1] = kc.
+extern "C" void host_choose_strips(int requested, int plain_one_wave, int nb, long long slots,
+                                   int *out)
+{
+    const sk::StripLayout L = sk::choose_strips(requested, plain_one_wave != 0, nb, slots);
+    out[0] = L.S;
+    out[1] = L.kc;
+}
