@@ -4,13 +4,15 @@
 //
 // The pairs of blocks (I, J), I <= J, of 64 particles are the tiles of the
 // upper triangle.  A tile writes the sums its pairs give block J (the j side)
-// to part[J][I]; the sums they give block I (the i side) go to part[I][J0],
-// where J0 is the first tile of the work item that covers (I, J): a row strip
-// of tiles (I, J0), ..., (I, J0 + len - 1) keeps the i-side sums of block I in
-// one place and writes them once.  A row K (tiles J = K..nb-1, d = nb - K of
-// them) split into strips of S tiles holds d / S strips, the first starting
-// at the diagonal, and d mod S items of one tile: its last d mod S columns.
-// The other rows are items of one tile.
+// to block J's slot for column I; the sums they give block I (the i side) go
+// to block I's slot for column J0, the first tile of the work item that
+// covers (I, J): a row strip of tiles (I, J0), ..., (I, J0 + len - 1) keeps
+// the i-side sums of block I in one place and writes them once.  A row K
+// (tiles J = K..nb-1, d = nb - K of them) split into strips of S tiles holds
+// d / S strips, the first starting at the diagonal, and d mod S items of one
+// tile: its last d mod S columns.  The other rows are items of one tile.
+// Block K's slots are stored one after the other in k_apply's order
+// (apply_offset, item_slot).
 #pragma once
 #include <cmath>
 
