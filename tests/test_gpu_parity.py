@@ -162,6 +162,30 @@ def test_parity_row_strips(torch, oracle, n):
     assert sd["pair_solves"] == int(np.sum(sd["hist"]))
 
 
+def test_parity_default_strips_ragged(torch, lib, oracle):
+    """The default layout where it splits: n = 12345 (193 blocks, the last one
+    holding 57 particles) runs strips of 4 tiles in the rows of blocks 0..64
+    and single tiles in the triangle of the last 128 blocks on 256 compute
+    units; every row against the oracle's step, the exact pair-solve count, and
+    the same step with one tile per item (row_strip = 1) within rounding."""
+    from paper_1402_3325_amd.sakura import Sakura
+    n = 12345
+    m, r, v, tau = workloads.cluster(n_stars=n - 1, rng=np.random.default_rng(7300))
+    rg, vg, st = gpu_step(torch, lib, m, r, v, tau, stats=True)
+    assert st["pair_solves"] == n * (n - 1) // 2
+    ro, vo = oracle.step(m, r, v, tau)
+    er, ev = step_error(rg, vg, ro, vo, r, v)
+    print(f"n={n} default layout err {er:.2e} {ev:.2e}", flush=True)
+    assert er <= TOL and ev <= TOL
+    h1 = Sakura(0, row_strip=1)
+    try:
+        r1, v1, s1 = gpu_step(torch, h1, m, r, v, tau, stats=True)
+    finally:
+        h1.close()
+    assert s1["iters_total"] == st["iters_total"]
+    assert max(step_error(rg, vg, r1, v1, r, v)) <= 1e-14
+
+
 def _cluster_rows(m, r, rng, count=64, tight=32):
     """Rows to sample in a cluster: the central mass (row 0), the `tight`
     stars closest to a neighbour (members of the tightest binaries) with those
