@@ -35,10 +35,12 @@ def _both(torch, h, m, r, v, tau, nsteps):
     return (ra, va, sa), (rb, vb, sb)
 
 
-@pytest.mark.parametrize("warm", [False, True])
-def test_noalloc_equals_evolve_two_calls(torch, warm):
+@pytest.mark.parametrize("warm,strip", [(False, 0), (True, 0), (False, 4)])
+def test_noalloc_equals_evolve_two_calls(torch, warm, strip):
+    """strip = 4: work items of four tiles along a row in every row, the partial
+    sums in that layout's compact order inside the static scratch."""
     from paper_1402_3325_amd.sakura import NOALLOC_MAX_N, Sakura
-    h = Sakura(0)
+    h = Sakura(0, row_strip=strip)
     try:
         if warm:  # the handle's own buffers already hold a larger system
             m, r, v, tau = workloads.plummer(5000, rng=np.random.default_rng(3))
