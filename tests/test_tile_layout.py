@@ -43,6 +43,9 @@ def lay(tmp_path_factory):
         L.host_choose_strips(requested, int(plain), nb, slots, out.ctypes.data_as(IP))
         return int(out[0]), int(out[1])
     items.choose = choose
+    L.host_check_layout.restype = ctypes.c_longlong
+    L.host_check_layout.argtypes = [ctypes.c_int] * 3
+    items.check = L.host_check_layout
     L.host_apply_offset.restype = ctypes.c_longlong
     L.host_apply_offset.argtypes = [ctypes.c_int] * 4
     L.host_item_slot.argtypes = [ctypes.c_int] * 5
@@ -150,3 +153,15 @@ def test_chosen_layouts_are_valid(lay):
         for req in (0, 4, 64):
             S, kc = items.choose(req, True, nb, 64)
             _check(lay, nb, S, kc)
+
+
+@pytest.mark.parametrize("nb", [1000, 4096])
+def test_large_layouts_cover_every_tile_once(lay, nb):
+    """The chosen layouts at 64,000 and 262,144 particles (the default and strips
+    of 4 and 64 in every row), counted in C++: every tile covered once, every
+    slot of the compact storage written once, the slot count below 2^31."""
+    items, slots = lay
+    for req in (0, 4, 64):
+        S, kc = items.choose(req, True, nb, 4096)
+        assert items.check(nb, S, kc) == 0, (nb, req, S, kc)
+        assert slots.offset(nb, nb, S, kc) < 2 ** 31

@@ -2,6 +2,7 @@
 // tiles.hpp), for the CPU test of its coverage (tests/test_tile_layout.py).
 #include <cmath>
 #include <cstdint>
+#include <vector>
 using std::fmax;
 using std::sqrt;
 #define SAKURA_TILES_HD
@@ -49,4 +50,38 @@ extern "C" void host_choose_strips(int requested, int plain_one_wave, int nb, lo
     const sk::StripLayout L = sk::choose_strips(requested, plain_one_wave != 0, nb, slots);
     out[0] = L.S;
     out[1] = L.kc;
+}
+
+// Every tile covered once and every slot of the compact storage written once,
+// counted in C++ for large block counts: the number of violations.
+extern "C" long long host_check_layout(int nb, int S, int kc)
+{
+    const sk::StripLayout L{S, kc};
+    std::vector<long long> off(nb + 1);
+    for (int K = 0; K <= nb; ++K) off[K] = sk::apply_offset(K, nb, L);
+    std::vector<unsigned char> cover((size_t)nb * nb, 0), slot((size_t)off[nb], 0);
+    long long bad = 0;
+    const long long n = sk::layout_items(nb, L);
+    for (long long t = 0; t < n; ++t) {
+        int I, J0, len;
+        sk::layout_item(t, nb, L, I, J0, len);
+        if (I < 0 || J0 < I || len < 1 || J0 + len > nb) {
+            ++bad;
+            continue;
+        }
+        for (int J = J0; J < J0 + len; ++J) {
+            ++cover[(size_t)I * nb + J];
+            if (J == I) continue;
+            const long long sj = off[J] + I; // the j side
+            if (sj >= off[J + 1]) ++bad;
+            else ++slot[(size_t)sj];
+        }
+        const long long si = off[I] + sk::item_slot(I, J0, nb, L);
+        if (si < off[I] || si >= off[I + 1]) ++bad;
+        else ++slot[(size_t)si];
+    }
+    for (int I = 0; I < nb; ++I)
+        for (int J = 0; J < nb; ++J) bad += cover[(size_t)I * nb + J] != (J >= I ? 1 : 0);
+    for (long long k = 0; k < off[nb]; ++k) bad += slot[(size_t)k] != 1;
+    return bad;
 }
