@@ -162,7 +162,10 @@ __device__ inline bool hybrid_close(double t2, double mu, double r2, double w2, 
     return (A * A > e4 * ((r2 * r2) * r2)) | (t2 * w2 > e2 * r2);
 }
 
-// All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront.
+// All unordered pairs of one 64 x 64 tile (I, J), I <= J, by one wavefront;
+// in the plain kernels of one wavefront per tile a work item may be a strip of
+// tiles (I, J0), ..., (I, J0 + len - 1) along a row (tiles.hpp), taken one
+// after the other with block I's particles and i-side sums kept.
 //
 // Lane l holds particle i = 64 I + l and its i-side sums in registers; block
 // J sits in LDS.  In sub-step s lane l takes the pair
@@ -943,8 +946,9 @@ int pair_split(int ntiles, int cus)
     return split;
 }
 
-// One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one),
-// or one wavefront per strip of `strip` tiles (pair_strip).
+// One tile-kernel launch with SPLIT wavefronts per tile (mode 4 always one);
+// with SPLIT 1 one wavefront per work item of the layout `strips`
+// (choose_strips in tiles.hpp).
 template <bool HIST, int MODE, bool DEFKP = false, bool HALVES = false>
 void launch_tiles(int split, StripLayout strips, int ntiles, hipStream_t st, int n, int nb,
                   int np, double dt, double cb, double ca, double G, double e2, double e4, const double *S,
