@@ -406,16 +406,22 @@ def test_max_iter_limit(torch):
     h.close()
 
 
-def test_default_parameters_kernel_matches_general(torch, lib):
+@pytest.mark.parametrize("strip", [0, 4])
+def test_default_parameters_kernel_matches_general(torch, lib, strip):
     """The tile kernel built for the default solver parameters and the general
-    one (any other max_iter) do the same arithmetic: identical results."""
+    one (any other max_iter) do the same arithmetic: identical results, with
+    the default layout (tiles split over wavefronts at this size) and with
+    strips of 4 tiles in every row (the general kernel's strip loop)."""
     from paper_1402_3325_amd.sakura import Sakura
     m, r, v, tau = workloads.plummer(4096, rng=np.random.default_rng(5))
-    hg = Sakura(0, max_iter=41)
+    hd = Sakura(0, row_strip=strip) if strip else lib
+    hg = Sakura(0, max_iter=41, row_strip=strip)
     try:
-        ra, va, sa = gpu_step(torch, lib, m, r, v, tau, nsteps=2, stats=True)
+        ra, va, sa = gpu_step(torch, hd, m, r, v, tau, nsteps=2, stats=True)
         rb, vb, sb = gpu_step(torch, hg, m, r, v, tau, nsteps=2, stats=True)
     finally:
         hg.close()
+        if strip:
+            hd.close()
     assert np.array_equal(ra, rb) and np.array_equal(va, vb)
     assert sa["iters_total"] == sb["iters_total"] and sa["pair_solves"] == sb["pair_solves"]

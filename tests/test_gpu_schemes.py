@@ -89,6 +89,28 @@ def test_scheme_parity_planetary_every_step(torch, lib, oracle, scheme):
 
 
 @pytest.mark.parametrize("scheme", ["unmerged", "triple_jump"])
+def test_scheme_parity_row_strips(torch, oracle, scheme):
+    """The stages' pair launches with work items of 4 tiles along a row
+    (opts.row_strip; the drift split of eqs. 19a/b runs the kernel that forms
+    the increments outside the solver) on 1000 particles, forward and backward
+    in time, against the oracle's scheme step."""
+    from paper_1402_3325_amd.sakura import Sakura
+    m, r, v, tau = workloads.cluster(n_stars=999, rng=np.random.default_rng(2400))
+    sid = SCHEMES[scheme][0]
+    h = Sakura(0, row_strip=4)
+    try:
+        for dt in (tau, -2.0 * tau):
+            rg, vg, st = gpu_scheme(torch, h, m, r, v, dt, scheme, stats=True)
+            assert st["pair_solves"] == SCHEMES[scheme][1] * 1000 * 999 // 2
+            tol, (ro, vo) = conditioned_tol(oracle, m, r, v, dt, sid)
+            er, ev = step_error(rg, vg, ro, vo, r, v)
+            print(scheme, "strips of 4", dt, "err", er, ev, "tol", tol)
+            assert er <= tol and ev <= tol, (scheme, dt, er, ev, tol)
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("scheme", ["unmerged", "triple_jump"])
 @pytest.mark.parametrize("n", [2, 3, 65, 333, 1000])
 def test_scheme_parity_ragged_sizes(torch, lib, oracle, scheme, n):
     """Sizes around the 64-particle tile with ragged tails, forward and
