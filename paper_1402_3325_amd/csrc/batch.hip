@@ -436,6 +436,18 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
     // one wavefronts per item); the items of each launch stay in the order they
     // were opened, largest first.
     const int ov = h->opts.tile_override;
+    // A call with the same systems and packing settings as the last one
+    // reuses its packing, already on the device (a repeated call, as in a
+    // time loop, then costs no host work before its launches).
+    const bool same_plan =
+        h->plan_dev != nullptr && h->plan_dev == h->batch_work && h->plan_override == ov &&
+        (int64_t)h->plan_offsets.size() == nsys + 1 &&
+        std::equal(offsets, offsets + nsys + 1, h->plan_offsets.begin()) &&
+        std::memcmp(h->plan_group, h->batch_group, sizeof h->plan_group) == 0 &&
+        std::memcmp(h->plan_width, h->batch_width, sizeof h->plan_width) == 0;
+    int nitems = h->plan_nitems;
+    int nw[3] = {h->plan_nw[0], h->plan_nw[1], h->plan_nw[2]};
+    if (!same_plan) {
     std::vector<int> Ls((size_t)nsys), order((size_t)nsys);
     for (int64_t s = 0; s < nsys; ++s) {
         const int n = (int)(offsets[s + 1] - offsets[s]);
@@ -465,7 +477,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         bin_of[(size_t)sy] = bin;
         if (bin_free[(size_t)bin] > 0) by_free[bin_free[(size_t)bin]].push_back(bin);
     }
-    const int nitems = (int)bin_free.size();
+    nitems = (int)bin_free.size();
     // the lane table: (system, l | L << 8) per lane, (-1, 0) on free lanes
     std::vector<int> lane_tab((size_t)nitems * TILE * 2);
     for (size_t e = 0; e < lane_tab.size(); e += 2) {
@@ -484,7 +496,7 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         ++count[(size_t)bin];
     }
     // items of 4, 2 and 1 wavefronts, in that order
-    int nw[3] = {0, 0, 0};
+    nw[0] = nw[1] = nw[2] = 0;
     std::vector<int> items;
     items.reserve(4 * (size_t)nitems);
     for (int cls = 0; cls < 3; ++cls)
@@ -499,17 +511,31 @@ int sakura_batch_evolve(sakura_t *h, int64_t nsys, const int64_t *offsets, const
         }
     h->host_work.assign(items.begin(), items.end());
     h->host_work.insert(h->host_work.end(), lane_tab.begin(), lane_tab.end());
+    }
 
     SAKURA_HIP(h, hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
     int rc;
     if ((rc = grow(h, &h->batch_state, &h->cap_batch, 6 * ntot))) return rc;
-    if ((rc = grow(h, &h->batch_work, &h->cap_work, (int64_t)h->host_work.size()))) return rc;
-    if ((rc = grow(h, &h->batch_offsets, &h->cap_offsets, nsys + 1))) return rc;
-    SAKURA_HIP(h, hipMemcpyAsync(h->batch_work, h->host_work.data(),
-                                 h->host_work.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    SAKURA_HIP(h, hipMemcpyAsync(h->batch_offsets, offsets, (size_t)(nsys + 1) * sizeof(int64_t),
-                                 hipMemcpyHostToDevice, st));
+    if (!same_plan) {
+        h->plan_dev = nullptr; // until the new packing is on the device
+        if ((rc = grow(h, &h->batch_work, &h->cap_work, (int64_t)h->host_work.size())))
+            return rc;
+        if ((rc = grow(h, &h->batch_offsets, &h->cap_offsets, nsys + 1))) return rc;
+        SAKURA_HIP(h, hipMemcpyAsync(h->batch_work, h->host_work.data(),
+                                     h->host_work.size() * sizeof(int), hipMemcpyHostToDevice,
+                                     st));
+        SAKURA_HIP(h, hipMemcpyAsync(h->batch_offsets, offsets,
+                                     (size_t)(nsys + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                                     st));
+        h->plan_offsets.assign(offsets, offsets + nsys + 1);
+        std::memcpy(h->plan_group, h->batch_group, sizeof h->plan_group);
+        std::memcpy(h->plan_width, h->batch_width, sizeof h->plan_width);
+        h->plan_override = ov;
+        h->plan_nitems = nitems;
+        for (int k = 0; k < 3; ++k) h->plan_nw[k] = nw[k];
+        h->plan_dev = h->batch_work;
+    }
     const bool timing = stats != nullptr;
     if (timing) {
         while (h->events.size() < 2) {

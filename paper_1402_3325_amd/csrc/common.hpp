@@ -149,6 +149,13 @@ struct sakura {
     int64_t *batch_offsets = nullptr;
     int64_t cap_offsets = 0;
     std::vector<int> host_work;
+    // the packing last uploaded to batch_work and batch_offsets, and what it
+    // was made from: the systems' offsets, the lanes and widths per system
+    // size, the override, the device buffer it went to
+    std::vector<int64_t> plan_offsets;
+    int plan_group[65] = {0}, plan_width[65] = {0};
+    int plan_override = -1, plan_nitems = 0, plan_nw[3] = {0, 0, 0};
+    const int *plan_dev = nullptr;
     hipStream_t capture_stream = nullptr;
     hipStream_t capture_stream2 = nullptr; // further branches of the captured batch graph
     hipStream_t capture_stream3 = nullptr;
