@@ -289,6 +289,42 @@ def test_graph_follows_a_new_ensemble_in_the_same_buffers(torch, lib):
     assert np.array_equal(vt[:nb].cpu().numpy(), v2.cpu().numpy())
 
 
+def test_packing_follows_the_settings(torch, lib):
+    """A call with the same systems as the last one reuses its packing of lane
+    groups into work items; a change of the lanes given to one system size
+    (batch_set_group) or of the override must pack again: each call equals the
+    same call on a fresh handle with the same settings, bit for bit, also when
+    the handle goes back to the first settings."""
+    from paper_1402_3325_amd.sakura import Sakura
+    lib.batch_set_policy(0, 8, True)
+    off, m, r, v, t = small_ensemble([5, 9, 17, 33, 3, 64, 12, 9], seed=43)
+
+    def run(h):
+        mt, rt, vt, dtt = _dev(torch, m, r, v, t)
+        h.batch_evolve(off, mt, rt, vt, dtt, 2)
+        torch.cuda.synchronize()
+        return rt.cpu().numpy(), vt.cpu().numpy()
+
+    first = run(lib)
+    again = run(lib)  # the reused packing
+    assert np.array_equal(first[0], again[0]) and np.array_equal(first[1], again[1])
+    lib.batch_set_group(9, 16)
+    try:
+        wide = run(lib)
+        fresh = Sakura(0)
+        try:
+            fresh.batch_set_policy(0, 8, True)
+            fresh.batch_set_group(9, 16)
+            ref = run(fresh)
+        finally:
+            fresh.close()
+        assert np.array_equal(wide[0], ref[0]) and np.array_equal(wide[1], ref[1])
+    finally:
+        lib.batch_set_policy(0, 8, True)
+    back = run(lib)
+    assert np.array_equal(first[0], back[0]) and np.array_equal(first[1], back[1])
+
+
 def test_batch_step_sizes_must_be_on_the_device(torch, lib):
     off, m, r, v, tau = small_ensemble([5, 3])
     mt, rt, vt = _dev(torch, m, r, v)
